@@ -1,0 +1,178 @@
+/*
+ * gwc.h - C ABI of libgwc: the G0W0 correlation self-energy of core states by
+ * contour deformation (CD) with the resolution of the identity (RI), and the
+ * GW+C cumulant spectral function, on one AMD MI355X (gfx950).
+ *
+ * Paper: Kocklauner & Golze, "GW plus cumulant approach for predicting
+ * core-level shake-up satellites in large molecules" (arXiv:2412.17132).
+ *
+ * Conventions for every entry point
+ *   - Energies and frequencies in Hartree; arrays are row-major float64;
+ *     sizes are int32.
+ *   - The caller owns every buffer.  A pointer may address host memory or
+ *     device memory of the current HIP device; the library detects which and
+ *     stages host data itself.  No pointer is kept after the call returns.
+ *   - Calls are synchronous: they return after the outputs are written.  All
+ *     device work is ordered on `hip_stream` (NULL = the default stream).
+ *   - On error the outputs are unspecified, the status below is returned, no
+ *     exception crosses the ABI and the process is never aborted;
+ *     gwc_last_error() then describes the failure (thread-local).
+ *   - Concurrent calls on one device from several host threads are
+ *     serialised by the library.
+ */
+#ifndef GWC_H
+#define GWC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GWC_VERSION 10000 /* 1.0.0 */
+
+enum gwc_status {
+  GWC_OK = 0,
+  GWC_ERR_INVALID_ARG = -1,     /* NULL pointer, unknown mode/precision, bad grid order */
+  GWC_ERR_SHAPE = -2,           /* a size < 1, core index out of range, size too large */
+  GWC_ERR_NONPOSITIVE_GAP = -3, /* max eps_occ >= min eps_virt: chi would change sign */
+  GWC_ERR_NONFINITE = -4,       /* NaN/Inf in an input */
+  GWC_ERR_FACTORIZATION = -5,   /* exactly singular pivot in the LU of 1 - Pi(z) */
+  GWC_ERR_OUT_OF_MEMORY = -6,
+  GWC_ERR_DEVICE = -7,          /* any other HIP runtime failure */
+  GWC_ERR_UNSUPPORTED = -8      /* a valid request this build does not implement */
+};
+
+enum gwc_mode {
+  /* Sigma^c_n on every real grid point with all residue terms
+   * (Eqs. cd_terms, cd_imaginary, cd_residue, cd_prefactors). */
+  GWC_MODE_FULL = 0,
+  /* Decoupling approximation (Eq. cd_sigma_imaginary_decoupled): on the grid
+   * only the m = n residue, giving Im Sigma^dec; Sigma^c_n(eps_n) is still
+   * computed with every term for the quasiparticle energy. */
+  GWC_MODE_DECOUPLED = 1
+};
+
+enum gwc_precision {
+  GWC_PREC_FP64 = 0,   /* everything in float64 */
+  GWC_PREC_BF16X3 = 1, /* Pi build as hi*hi + hi*lo + lo*hi bf16 products, fp32 accumulation */
+  GWC_PREC_FP16X3 = 2, /* same with fp16 and power-of-two scaling */
+  GWC_PREC_FP8 = 3     /* reserved */
+};
+
+/* A closed-shell system in the RI representation.
+ * Orbitals are ordered occupied first: m < n_occ occupied (occ = 2),
+ * m >= n_occ virtual (occ = 0); n_basis = n_occ + n_virt.
+ *   eps  [n_basis]              Kohn-Sham eigenvalues (Ha)
+ *   occ  [n_basis]              occupations, each exactly 2.0 or 0.0, occupied first
+ *   M_oo [n_aux][n_occ][n_occ]  RI coefficients M^P_ij (Coulomb-metric symmetrised,
+ *                               so that W = (1 - Pi)^-1 - 1 in this basis)
+ *   M_ov [n_aux][n_occ][n_virt] RI coefficients M^P_ia
+ * M_vv is never needed: the states n are occupied, so every pair (n, m) lies
+ * in the oo or ov block. */
+typedef struct {
+  int32_t n_aux, n_occ, n_virt;
+  const double *eps;
+  const double *occ;
+  const double *M_oo;
+  const double *M_ov;
+} gwc_system;
+
+/* Arguments of gwc_sigma_core.
+ *   core_idx   [n_core]          occupied states n (each < n_occ), the "core states"
+ *   omega_imag [n_imag], w_imag  nodes (> 0, strictly increasing) and weights (> 0)
+ *                                of a quadrature for int_0^inf (imaginary axis)
+ *   omega_real [n_core][n_real]  real frequencies per core state, strictly increasing
+ *   eta        > 0               broadening of the residue arguments |eps_m - w| + i eta
+ *   vxc        [n_core] or NULL  <n|v_xc|n>, NULL means 0
+ *   mode       enum gwc_mode; precision enum gwc_precision */
+typedef struct {
+  int32_t n_core;
+  const int32_t *core_idx;
+  int32_t n_imag;
+  const double *omega_imag;
+  const double *w_imag;
+  int32_t n_real;
+  const double *omega_real;
+  double eta;
+  const double *vxc;
+  int32_t mode;
+  int32_t precision;
+} gwc_sigma_args;
+
+/* Outputs of gwc_sigma_core (each may be host or device memory).
+ *   sigma_c      [n_core][n_real][2]  Sigma^c_n(w) = -I_n(w) + R_n(w) as (re, im);
+ *                                     required in FULL mode, ignored (may be NULL)
+ *                                     in DECOUPLED mode
+ *   im_sigma_dec [n_core][n_real]     f_n Im W^c_nn(|eps_n - w| + i eta), or NULL
+ *   sigma_c_eps  [n_core][2]          Sigma^c_n(eps_n) (re, im), or NULL
+ *   sigma_x      [n_core]             Sigma^x_n = -sum_i (n i|i n), or NULL
+ *   e_qp         [n_core]             E_QP = eps_n + Sigma^x_n + Re Sigma^c_n(eps_n) - v^xc_n
+ *                                     (Eq. QPGWC), or NULL */
+typedef struct {
+  double *sigma_c;
+  double *im_sigma_dec;
+  double *sigma_c_eps;
+  double *sigma_x;
+  double *e_qp;
+} gwc_sigma_out;
+
+/* Correlation self-energy of the requested core states by contour
+ * deformation (paper section "Self-energy evaluation"):
+ *   Sigma^c_n(w) = -I_n(w) + R_n(w)                                (Eq. cd_terms)
+ *   I_n(w) = (1/pi) sum_k w_k sum_m W^c_nm(i w_k) a/(a^2 + w_k^2),
+ *            a = w - eps_m                 (Eq. cd_imaginary, folded to (0, inf))
+ *   R_n(w) = sum_m f_m W^c_nm(|eps_m - w| + i eta)                  (Eq. cd_residue)
+ *   f_m    = -Theta(eps_F - eps_m) Theta(eps_m - w)
+ *            + Theta(eps_m - eps_F) Theta(w - eps_m), Theta(0) = 1/2 (Eq. cd_prefactors)
+ * with the RI screened interaction W^c_nm(z) = M_nm^T [(1 - Pi(z))^-1 - 1] M_nm,
+ * Pi_PQ(z) = sum_ia M^P_ia M^Q_ia 4 Delta_ia / (z^2 - Delta_ia^2).
+ * Returns GWC_OK or a negative gwc_status. */
+int gwc_sigma_core(const gwc_system *sys, const gwc_sigma_args *args, gwc_sigma_out *out,
+                   void *hip_stream);
+
+/* Arguments of gwc_spectral_cumulant (one core state).
+ *   omega_real [n_real], im_sigma [n_real]  Im Sigma^c_n on a strictly increasing
+ *                                          grid in the G0W0 frame (zero outside it)
+ *   eps_n, e_qp        the mean-field level and the GW+C quasiparticle energy
+ *   eta > 0            broadening of G^QP_0 (Eq. eq:GQP)
+ *   n_t                number of time points = FFT length, a power of two in [2^4, 2^24]
+ *   d_omega > 0        frequency resolution; dt = 2 pi / (n_t d_omega)
+ *   n_out in [1, n_t]  number of output frequencies omega_out_min + l d_omega */
+typedef struct {
+  int32_t n_real;
+  const double *omega_real;
+  const double *im_sigma;
+  double eps_n, e_qp, eta;
+  int32_t n_t;
+  double d_omega;
+  int32_t n_out;
+  double omega_out_min;
+} gwc_cumulant_args;
+
+/* GW+C spectral function of one state (paper section "Numerical GW+C scheme"):
+ *   C~(t) = (1/pi) int dw |Im Sigma^c_n(w + eps_n)| / w^2 (e^{-iwt} - 1)
+ *                                      (Eq. landau_cumulant_truncated; trapezoid
+ *                                       sum on the grid, the w = 0 term is 0)
+ *   G^C(t) = -i Theta(t) e^{-i E_QP t - eta t} e^{C~(t)}, Theta(0) = 1/2
+ *                                      (Eq. cumulant_propagator_numerical_time)
+ *   G^C(w) = dt sum_k G^C(t_k) e^{i w t_k} by FFT    (Eqs. cumulant_propagator_fourier,
+ *                                                     cumulant_propagator_convolution)
+ *   A(w)   = -Im G^C(w) / pi                         (Eq. eq:AGWC)
+ *   A_out [n_out]            spectral function on omega_out_min + l d_omega
+ *   z_out [2] or NULL        (Z, 1 - Z) with Z = exp(-(1/pi) int |Im Sigma| / w^2)
+ * Returns GWC_OK or a negative gwc_status. */
+int gwc_spectral_cumulant(const gwc_cumulant_args *args, double *A_out, double *z_out,
+                          void *hip_stream);
+
+/* Message describing the last non-OK return on the calling thread ("" if none). */
+const char *gwc_last_error(void);
+
+/* GWC_VERSION of the loaded library. */
+int gwc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWC_H */

@@ -1,0 +1,8 @@
+"""MI355X-native GW+C core-level path: contour-deformation Sigma^c of core
+states with the RI polarisability built on FP64 MFMA, and the cumulant
+spectral function.  The compute lives in libgwc.so (HIP, gfx950); this
+package is its Python binding."""
+from ._native import GwcError
+from .api import gwc_sigma_core, gwc_spectral_cumulant, to_device, version
+
+__all__ = ["GwcError", "gwc_sigma_core", "gwc_spectral_cumulant", "to_device", "version"]

@@ -1,0 +1,109 @@
+"""ctypes declarations of the libgwc C ABI (include/gwc.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  The library must have been built (``__graft_entry__.build()``);
+loading fails loudly otherwise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, c_double, c_int, c_int32, c_void_p
+
+LIB_NAME = "libgwc.so"
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), LIB_NAME)
+
+GWC_OK = 0
+STATUS_NAMES = {
+    0: "GWC_OK",
+    -1: "GWC_ERR_INVALID_ARG",
+    -2: "GWC_ERR_SHAPE",
+    -3: "GWC_ERR_NONPOSITIVE_GAP",
+    -4: "GWC_ERR_NONFINITE",
+    -5: "GWC_ERR_FACTORIZATION",
+    -6: "GWC_ERR_OUT_OF_MEMORY",
+    -7: "GWC_ERR_DEVICE",
+    -8: "GWC_ERR_UNSUPPORTED",
+}
+MODES = {"full": 0, "decoupled": 1}
+PRECISIONS = {"fp64": 0, "bf16x3": 1, "fp16x3": 2, "fp8": 3}
+
+EXPORTED_SYMBOLS = (
+    "gwc_sigma_core",
+    "gwc_spectral_cumulant",
+    "gwc_last_error",
+    "gwc_version",
+)
+
+
+class GwcSystem(Structure):
+    _fields_ = [
+        ("n_aux", c_int32), ("n_occ", c_int32), ("n_virt", c_int32),
+        ("eps", c_void_p), ("occ", c_void_p), ("M_oo", c_void_p), ("M_ov", c_void_p),
+    ]
+
+
+class GwcSigmaArgs(Structure):
+    _fields_ = [
+        ("n_core", c_int32), ("core_idx", c_void_p),
+        ("n_imag", c_int32), ("omega_imag", c_void_p), ("w_imag", c_void_p),
+        ("n_real", c_int32), ("omega_real", c_void_p),
+        ("eta", c_double), ("vxc", c_void_p),
+        ("mode", c_int32), ("precision", c_int32),
+    ]
+
+
+class GwcSigmaOut(Structure):
+    _fields_ = [
+        ("sigma_c", c_void_p), ("im_sigma_dec", c_void_p), ("sigma_c_eps", c_void_p),
+        ("sigma_x", c_void_p), ("e_qp", c_void_p),
+    ]
+
+
+class GwcCumulantArgs(Structure):
+    _fields_ = [
+        ("n_real", c_int32), ("omega_real", c_void_p), ("im_sigma", c_void_p),
+        ("eps_n", c_double), ("e_qp", c_double), ("eta", c_double),
+        ("n_t", c_int32), ("d_omega", c_double),
+        ("n_out", c_int32), ("omega_out_min", c_double),
+    ]
+
+
+class GwcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.status_name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{self.status_name}: {message}")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgwc (once).  torch is imported first so that the library binds
+    to the same HIP runtime instance as torch's allocator and streams."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(the GPU path has no fallback)")
+    import torch  # noqa: F401  (one HIP runtime per process)
+    lib = ctypes.CDLL(path)
+    lib.gwc_sigma_core.argtypes = [POINTER(GwcSystem), POINTER(GwcSigmaArgs),
+                                   POINTER(GwcSigmaOut), c_void_p]
+    lib.gwc_sigma_core.restype = c_int
+    lib.gwc_spectral_cumulant.argtypes = [POINTER(GwcCumulantArgs), c_void_p, c_void_p, c_void_p]
+    lib.gwc_spectral_cumulant.restype = c_int
+    lib.gwc_last_error.argtypes = []
+    lib.gwc_last_error.restype = ctypes.c_char_p
+    lib.gwc_version.argtypes = []
+    lib.gwc_version.restype = c_int
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != GWC_OK:
+        msg = _lib.gwc_last_error().decode() if _lib is not None else ""
+        raise GwcError(status, msg)

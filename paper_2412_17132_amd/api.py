@@ -1,0 +1,138 @@
+"""Python binding of libgwc: the same entry points as the C ABI, argument
+marshalling only.
+
+Arrays may be torch tensors (CUDA/HIP device or CPU) or NumPy arrays; device
+tensors are passed by pointer, host arrays are staged by the library itself.
+Outputs are allocated on the device of `M_ov` unless given.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+from . import _native as N
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _is_tensor(x) -> bool:
+    try:
+        return isinstance(x, _torch().Tensor)
+    except ImportError:  # pragma: no cover
+        return False
+
+
+def _as_arg(x, dtype: str, keep: list):
+    """Pointer of a contiguous array of the given dtype ('f8' or 'i4')."""
+    if x is None:
+        return None
+    if _is_tensor(x):
+        torch = _torch()
+        want = torch.float64 if dtype == "f8" else torch.int32
+        if x.dtype != want or not x.is_contiguous():
+            x = x.to(want).contiguous()
+        keep.append(x)
+        return x.data_ptr()
+    arr = np.ascontiguousarray(x, dtype=np.float64 if dtype == "f8" else np.int32)
+    keep.append(arr)
+    return arr.ctypes.data
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return stream
+    torch = _torch()
+    if torch.cuda.is_available():
+        return torch.cuda.current_stream().cuda_stream
+    return None
+
+
+def _alloc(shape, like):
+    if _is_tensor(like) and like.is_cuda:
+        torch = _torch()
+        return torch.empty(shape, dtype=torch.float64, device=like.device)
+    return np.empty(shape, dtype=np.float64)
+
+
+def gwc_sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_real, eta,
+                   vxc=None, mode: str = "full", precision: str = "fp64",
+                   out: Optional[dict] = None, stream=None) -> dict:
+    """Sigma^c_n(w) of the core states by contour deformation (gwc_sigma_core).
+
+    Returns a dict with sigma_c [n_core][n_real][2] (None in decoupled mode),
+    im_sigma_dec [n_core][n_real], sigma_c_eps [n_core][2], sigma_x, e_qp."""
+    lib = N.load()
+    n_aux, n_occ, n_virt = (int(s) for s in M_ov.shape)
+    n_core = int(core_idx.shape[0])
+    n_imag = int(omega_imag.shape[0])
+    n_real = int(omega_real.shape[-1])
+    keep: list = []
+    sys = N.GwcSystem(n_aux, n_occ, n_virt, _as_arg(eps, "f8", keep), _as_arg(occ, "f8", keep),
+                      _as_arg(M_oo, "f8", keep), _as_arg(M_ov, "f8", keep))
+    args = N.GwcSigmaArgs(n_core, _as_arg(core_idx, "i4", keep), n_imag,
+                          _as_arg(omega_imag, "f8", keep), _as_arg(w_imag, "f8", keep), n_real,
+                          _as_arg(omega_real, "f8", keep), float(eta), _as_arg(vxc, "f8", keep),
+                          N.MODES[mode], N.PRECISIONS[precision])
+    if out is None:
+        out = {
+            "sigma_c": _alloc((n_core, n_real, 2), M_ov) if mode == "full" else None,
+            "im_sigma_dec": _alloc((n_core, n_real), M_ov),
+            "sigma_c_eps": _alloc((n_core, 2), M_ov),
+            "sigma_x": _alloc((n_core,), M_ov),
+            "e_qp": _alloc((n_core,), M_ov),
+        }
+    o = N.GwcSigmaOut(*(_as_out(out.get(k)) for k in
+                        ("sigma_c", "im_sigma_dec", "sigma_c_eps", "sigma_x", "e_qp")))
+    N.check(lib.gwc_sigma_core(sys, args, o, _stream_handle(stream)))
+    return out
+
+
+def _as_out(x):
+    if x is None:
+        return None
+    if _is_tensor(x):
+        assert x.dtype == _torch().float64 and x.is_contiguous()
+        return x.data_ptr()
+    assert x.dtype == np.float64 and x.flags["C_CONTIGUOUS"]
+    return x.ctypes.data
+
+
+def gwc_spectral_cumulant(omega_real, im_sigma, eps_n, e_qp, eta, n_t, d_omega, n_out,
+                          omega_out_min, A_out=None, z_out=None, stream=None):
+    """GW+C spectral function of one state (gwc_spectral_cumulant).
+    Returns (A [n_out], z [2] = (Z, 1 - Z))."""
+    lib = N.load()
+    keep: list = []
+    n_real = int(omega_real.shape[0])
+    args = N.GwcCumulantArgs(n_real, _as_arg(omega_real, "f8", keep), _as_arg(im_sigma, "f8", keep),
+                             float(eps_n), float(e_qp), float(eta), int(n_t), float(d_omega),
+                             int(n_out), float(omega_out_min))
+    if A_out is None:
+        A_out = _alloc((int(n_out),), im_sigma)
+    if z_out is None:
+        z_out = _alloc((2,), im_sigma)
+    N.check(lib.gwc_spectral_cumulant(args, _as_out(A_out), _as_out(z_out), _stream_handle(stream)))
+    return A_out, z_out
+
+
+def to_device(system, device="cuda"):
+    """Device-resident copies (torch tensors) of a system's arrays."""
+    torch = _torch()
+
+    def t(x, dt=torch.float64):
+        return None if x is None else torch.as_tensor(np.ascontiguousarray(x)).to(device=device, dtype=dt)
+
+    return dict(
+        eps=t(system.eps), occ=t(system.occ), M_oo=t(system.M_oo), M_ov=t(system.M_ov),
+        core_idx=t(system.core_idx, torch.int32), omega_imag=t(system.omega_imag),
+        w_imag=t(system.w_imag), omega_real=t(system.omega_real), eta=float(system.eta),
+        vxc=t(getattr(system, "vxc", None)),
+    )
+
+
+def version() -> int:
+    return int(N.load().gwc_version())

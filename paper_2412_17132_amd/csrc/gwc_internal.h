@@ -1,0 +1,70 @@
+// Internal declarations shared by the host orchestration and the HIP kernels of
+// libgwc.  Everything here is gfx950-only HIP C++.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace gwc {
+
+// ---------------------------------------------------------------------------
+// Tiling constants of the FP64 polarisability build (one 64 x 64 output tile
+// per workgroup, 4 waves of 32 x 32, K staged through LDS in chunks of KC).
+constexpr int PI_TILE = 64;
+constexpr int PI_KC = 32;
+constexpr int PI_FB = 2;        // frequencies per workgroup (Re and Im each)
+constexpr int PI_THREADS = 256;
+
+// Rows of the packed L = M_ov matrix and its row stride are padded with zeros
+// to these multiples so the Pi kernel needs no bounds checks on loads.
+constexpr int L_ROW_ALIGN = PI_TILE;
+constexpr int L_COL_ALIGN = PI_KC;
+
+// Bordered LU (one workgroup per matrix).
+constexpr int LU_NB = 16;
+constexpr int LU_THREADS = 256;
+
+// ---------------------------------------------------------------------------
+// Launchers (all enqueue on `stream`, no synchronisation).
+void launch_pack_l(const double *M_ov, int n_aux, int n_ov, double *Lp, int n_aux_pad, int ldl,
+                   hipStream_t stream);
+void launch_chi(const double *eps, int n_occ, int n_virt, const double2 *z, int F, int ldl,
+                double *chi_re, double *chi_im, hipStream_t stream);
+void launch_pi_build_f64(const double *Lp, int ldl, int n_aux, const double *chi_re,
+                         const double *chi_im, int F, const int2 *tiles, int n_tiles,
+                         double2 *G, long long g_stride, int ldg, hipStream_t stream);
+void launch_border(const double *M_oo, const double *M_ov, int n_aux, int n_occ, int n_virt,
+                   const int *task_n, const int *task_m, int F, int R, double2 *G,
+                   long long g_stride, int ldg, double *bb, hipStream_t stream);
+void launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
+                        const double *bb, const long long *out_base, const int *out_stride,
+                        double2 *W_out, int *status, hipStream_t stream);
+
+void launch_sigma_x(const double *M_oo, int n_aux, int n_occ, const int *core_idx, int n_core,
+                    double *sigma_x, hipStream_t stream);
+void launch_quadrature(const double2 *W_imag, const double *eps, int n_basis,
+                       const double *omega_imag, const double *w_imag, int n_imag,
+                       const double *omega_real, int n_real, const int *core_idx, int n_core,
+                       int grid_points, double *I_out, hipStream_t stream);
+void launch_assemble(const double2 *W_real, const double *f_task, const int *task_m,
+                     const int *cj_offset, const int *cj_self, const double *I, int n_core,
+                     int n_real, const double *eps, const int *core_idx, const double *sigma_x,
+                     const double *vxc, int full, double *sigma_c, double *im_dec,
+                     double *sigma_c_eps, double *e_qp, hipStream_t stream);
+
+void launch_nonfinite(const double *x, long long n, int *flag, hipStream_t stream);
+
+// Cumulant tail.
+void launch_cumulant_weights(const double *omega_real, const double *im_sigma, int n_real,
+                             double eps_n, double *nu, double *c, double *z_out,
+                             hipStream_t stream);
+void launch_cumulant_time(const double *nu, const double *c, int n_real, int n_t, double dt,
+                          double e_qp, double omega0, double eta, double2 *Gt,
+                          hipStream_t stream);
+void launch_fft_inverse(double2 *buf_a, double2 *buf_b, int log2n, double2 **result,
+                        hipStream_t stream);
+void launch_extract_spectrum(const double2 *Gw, int n_out, double *A_out, hipStream_t stream);
+
+}  // namespace gwc

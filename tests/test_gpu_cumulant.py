@@ -1,0 +1,50 @@
+"""GPU parity of gwc_spectral_cumulant against the oracle, and its sum rule."""
+import numpy as np
+import pytest
+
+import paper_2412_17132_amd as gwc
+from oracle import cumulant as OC
+from workloads import EV_PER_HA
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+TOL = 1e-9
+
+
+def _case(seed, n_real=401):
+    rng = np.random.default_rng(seed)
+    eps_n = -10.65 + 0.01 * rng.standard_normal()
+    e_qp = eps_n - 0.8
+    w = np.linspace(eps_n - 25 / EV_PER_HA, eps_n, n_real)
+    im = np.zeros(n_real)
+    for _ in range(4):
+        c0 = rng.uniform(-24, -3) / EV_PER_HA
+        im -= rng.uniform(0.005, 0.05) * np.exp(-((w - eps_n - c0) / rng.uniform(0.01, 0.08)) ** 2)
+    return w, im, eps_n, e_qp
+
+
+@pytest.mark.parametrize("n_t,n_out", [(2 ** 14, 3000), (2 ** 18, 2600)])
+def test_cumulant_matches_oracle(n_t, n_out):
+    dev = torch.device("cuda:0")
+    w, im, eps_n, e_qp = _case(7)
+    eta, dw = 0.1 / EV_PER_HA, 0.01 / EV_PER_HA
+    w0 = e_qp - 22 / EV_PER_HA
+    print(f"cumulant n_t={n_t} n_out={n_out}", flush=True)
+    A, z = gwc.gwc_spectral_cumulant(torch.tensor(w, device=dev), torch.tensor(im, device=dev),
+                                     eps_n, e_qp, eta, n_t, dw, n_out, w0)
+    torch.cuda.synchronize()
+    Ar, Zr, Sr = OC.spectral_cumulant(w, im, eps_n, e_qp, eta, n_t, dw, n_out, w0)
+    A = A.cpu().numpy()
+    assert np.max(np.abs(A - Ar)) <= TOL * np.max(np.abs(Ar))
+    z = z.cpu().numpy()
+    assert abs(z[0] - Zr) <= 1e-12 and abs(z[1] - Sr) <= 1e-12
+
+
+def test_cumulant_sum_rule_and_host_pointers():
+    w, im, eps_n, e_qp = _case(8, n_real=301)
+    n_t, dw = 2 ** 13, 0.02 / EV_PER_HA
+    A, z = gwc.gwc_spectral_cumulant(w, im, eps_n, e_qp, 0.1 / EV_PER_HA, n_t, dw, n_t,
+                                     e_qp - 60 / EV_PER_HA)
+    assert isinstance(A, np.ndarray)
+    assert abs(np.sum(A) * dw - 1.0) < 1e-12
+    assert 0.0 < z[0] < 1.0

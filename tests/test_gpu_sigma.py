@@ -1,0 +1,145 @@
+"""GPU parity: libgwc (through the C ABI) against the FP64 CPU oracle.
+
+Bar (FP64 path): per core state, max_j |dSigma^c| / max_j |Sigma^c_oracle| <= 1e-9,
+and E_QP, Sigma^x, Im Sigma^dec to 1e-9 relative (Im Sigma^dec norm-wise).
+"""
+import numpy as np
+import pytest
+
+import paper_2412_17132_amd as gwc
+from oracle import sigma as OS
+from workloads import CONFIGS, EV_PER_HA, system_from_config
+from workloads.configs import small_config
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+TOL = 1e-9
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    return torch.device("cuda:0")
+
+
+def _run(s, mode="full", host=False):
+    if host:
+        return gwc.gwc_sigma_core(s.eps, s.occ, s.M_oo, s.M_ov, s.core_idx, s.omega_imag, s.w_imag,
+                                  s.omega_real, s.eta, vxc=s.vxc, mode=mode)
+    d = gwc.to_device(s, _dev())
+    out = gwc.gwc_sigma_core(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],
+                             d["omega_imag"], d["w_imag"], d["omega_real"], d["eta"], vxc=d["vxc"],
+                             mode=mode)
+    torch.cuda.synchronize()
+    return {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+
+
+def _cplx(a):
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def _compare(out, ref, mode="full"):
+    if mode == "full":
+        sc = _cplx(out["sigma_c"])
+        for c in range(sc.shape[0]):
+            scale = np.max(np.abs(ref["sigma_c"][c]))
+            err = np.max(np.abs(sc[c] - ref["sigma_c"][c])) / scale
+            assert err <= TOL, f"core {c}: sigma_c rel err {err:.3e}"
+            big = np.abs(ref["sigma_c"][c]) >= 1e-3 * scale
+            pw = np.max(np.abs(sc[c] - ref["sigma_c"][c])[big] / np.abs(ref["sigma_c"][c])[big])
+            assert pw <= TOL, f"core {c}: pointwise rel err {pw:.3e}"
+    imd = out["im_sigma_dec"]
+    scale = max(np.max(np.abs(ref["im_sigma_dec"])), 1e-300)
+    assert np.max(np.abs(imd - ref["im_sigma_dec"])) <= TOL * scale
+    assert np.allclose(out["sigma_x"], ref["sigma_x"], rtol=TOL, atol=0)
+    assert np.allclose(out["e_qp"], ref["e_qp"], rtol=TOL, atol=0)
+    se = _cplx(out["sigma_c_eps"])
+    assert np.max(np.abs(se - ref["sigma_c_eps"]) / np.abs(ref["sigma_c_eps"])) <= TOL
+
+
+SMALL = [
+    # n_occ, n_virt, n_aux, n_core, n_real, seed, extra
+    (3, 5, 12, 1, 9, 11, {}),
+    (4, 7, 70, 2, 6, 12, {}),                                   # 2 ragged Pi tiles, odd N_ov
+    (5, 11, 130, 3, 5, 13, {}),                                 # 3 tiles, tail of 2 rows
+    (4, 9, 65, 2, 12, 14, {"real_abs_ev": (-300.0, 15.0)}),     # grid crosses valence and virtuals
+    (6, 13, 17, 4, 4, 15, {"n_imag": 7}),                       # more cores than LU panel rows
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"occ{c[0]}_virt{c[1]}_aux{c[2]}" for c in SMALL])
+def test_small_systems_full(case):
+    n_occ, n_virt, n_aux, n_core, n_real, seed, extra = case
+    s = system_from_config(small_config(n_occ=n_occ, n_virt=n_virt, n_aux=n_aux, n_core=n_core,
+                                        n_real=n_real, seed=seed, **extra))
+    print(f"case occ={n_occ} virt={n_virt} aux={n_aux} core={n_core} real={n_real}", flush=True)
+    out = _run(s)
+    _compare(out, OS.sigma_core_system(s))
+
+
+def test_grid_points_on_orbital_energies():
+    """Grid points equal to eps_m exactly use Theta(0) = 1/2 (residue weight
+    -1/2, zero imaginary-axis term)."""
+    s = system_from_config(small_config(n_occ=4, n_virt=6, n_aux=20, n_core=1, n_real=6, seed=21,
+                                        real_abs_ev=(-300.0, -5.0)))
+    s.omega_real[0, 2] = s.eps[0]
+    s.omega_real[0, 4] = s.eps[2]
+    s.omega_real[0] = np.sort(s.omega_real[0])
+    assert len(np.unique(s.omega_real[0])) == s.omega_real.shape[1]
+    s.vxc = np.array([-0.25])
+    _compare(_run(s), OS.sigma_core_system(s))
+
+
+def test_c1_full_and_decoupled():
+    s = system_from_config(CONFIGS["c1"])
+    print("c1 full", flush=True)
+    out = _run(s, "full")
+    ref = OS.sigma_core_system(s, "full")
+    _compare(out, ref)
+    print("c1 decoupled", flush=True)
+    out_d = _run(s, "decoupled")
+    assert out_d["sigma_c"] is None
+    _compare(out_d, OS.sigma_core_system(s, "decoupled"), mode="decoupled")
+    # the m = n residue is the same task in both modes
+    assert np.array_equal(out_d["im_sigma_dec"], out["im_sigma_dec"])
+    assert np.array_equal(out_d["e_qp"], out["e_qp"])
+
+
+def test_host_and_device_pointers_agree():
+    s = system_from_config(small_config(n_occ=4, n_virt=7, n_aux=70, n_core=2, n_real=6, seed=31))
+    a = _run(s, host=False)
+    b = _run(s, host=True)
+    for k in a:
+        if a[k] is not None:
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_run_to_run_bitwise():
+    s = system_from_config(small_config(n_occ=5, n_virt=11, n_aux=130, n_core=3, n_real=5, seed=41))
+    a, b = _run(s), _run(s)
+    for k in a:
+        if a[k] is not None:
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_c2_size_sampled():
+    """Benzene-sized system (N_aux = 1200, N_ov = 5859, all 6 cores) with the
+    batch size of the benchmark; the oracle checks sampled points."""
+    s = system_from_config(CONFIGS["c2"], n_real=4)
+    print("c2-size full, 4 points per core", flush=True)
+    out = _run(s)
+    sc = _cplx(out["sigma_c"])
+    L = OS.ov_matrix(s.M_ov)
+    d = OS.transition_energies(s.eps, s.n_occ)
+    for c in (0, 5):
+        n = int(s.core_idx[c])
+        W = OS.w_imag_axis(L, d, s.M_oo, s.M_ov, [n], s.omega_imag)[0]
+        for j in (0, 3):
+            ref, imd, _ = OS.sigma_c_at(L, d, s.eps, s.occ, s.M_oo, s.M_ov, n,
+                                        float(s.omega_real[c, j]), s.eta, W, s.omega_imag, s.w_imag)
+            assert abs(sc[c, j] - ref) <= TOL * abs(ref), (c, j, sc[c, j], ref)
+            assert abs(out["im_sigma_dec"][c, j] - imd) <= TOL * abs(ref)
+        ref_eps, _, _ = OS.sigma_c_at(L, d, s.eps, s.occ, s.M_oo, s.M_ov, n, float(s.eps[n]), s.eta,
+                                      W, s.omega_imag, s.w_imag)
+        e_ref = s.eps[n] + OS.exchange(s.M_oo, n) + ref_eps.real
+        assert abs(out["e_qp"][c] - e_ref) <= TOL * abs(e_ref)
