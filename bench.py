@@ -1,0 +1,253 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the GW+C core-level path on one MI355X.
+
+One step = one pass of the whole path over the benzene-sized workload
+(N_basis = 300, N_occ = 21 with 6 C1s levels, N_aux = 1200, 32 imaginary and
+400 real frequencies per core, eta = 0.1 eV): gwc_sigma_core in FULL mode for
+all 6 core states (Pi builds, LUs, quadrature, residues, E_QP) followed by
+gwc_spectral_cumulant for each core (n_t = 2^18, 0.01 eV).  Inputs are
+resident in HBM before the timed region.  The metric is core-state solves per
+second (one solve = Sigma^c_n on its grid + E_QP + A_n(w)).
+
+Printed: one JSON line with the throughput, the Pi-build roofline (algorithmic
+FP64 flops / HIP-event kernel time against the 78.6 TFLOP/s FP64 MFMA peak)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "core-state Σc(ω) solves/sec + Π-build MFMA util; p50/p99 latency, mixed vs FP64"
+FP64_MFMA_PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pi_build_f64_c2_traffic.json")
+PI_SOURCE = os.path.join(ROOT, "paper_2412_17132_amd", "csrc", "kernels_pi.hip")
+
+
+def _sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _traffic_per_launch():
+    """HBM bytes per Pi-build launch from the committed rocprofv3 PMC summary,
+    or None when absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != _sha(PI_SOURCE):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(system, mode, n_tasks_per_core, budget_tasks=24):
+    """Times the oracle on a bounded sample and extrapolates to solves/s:
+    the imaginary axis of all cores, `budget_tasks` residue tasks, and one
+    cumulant at full size."""
+    import numpy as np
+
+    from oracle import cumulant as OC
+    from oracle import sigma as OS
+    from workloads import EV_PER_HA
+
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        for info in threadpool_info():
+            if info.get("internal_api") in ("openblas", "mkl", "blis"):
+                threads = int(info.get("num_threads"))
+                break
+    except Exception:
+        pass
+    if threads is None:
+        threads = os.cpu_count()
+
+    s = system
+    cores = [int(n) for n in s.core_idx]
+    L = OS.ov_matrix(s.M_ov)
+    d = OS.transition_energies(s.eps, s.n_occ)
+    t0 = time.perf_counter()
+    W = OS.w_imag_axis(L, d, s.M_oo, s.M_ov, cores, s.omega_imag)
+    t_imag = time.perf_counter() - t0
+
+    rng = np.random.default_rng(0)
+    done = 0
+    t0 = time.perf_counter()
+    while done < budget_tasks:
+        c = int(rng.integers(len(cores)))
+        j = int(rng.integers(s.omega_real.shape[1]))
+        n = cores[c]
+        for m, f, z in OS.residue_terms(s.eps, s.occ, float(s.omega_real[c, j]), s.eta):
+            OS.screened_element(L, d, OS.pair_vector(s.M_oo, s.M_ov, n, m), z)
+            done += 1
+            if done >= budget_tasks:
+                break
+    t_task = (time.perf_counter() - t0) / done
+
+    c = 0
+    n = cores[c]
+    im = np.zeros(s.omega_real.shape[1])
+    t0 = time.perf_counter()
+    I = OS.imag_integral(W[c], s.eps, s.omega_imag, s.w_imag, float(s.omega_real[c, 0]))
+    t_quad = (time.perf_counter() - t0) * (s.omega_real.shape[1] + 1)
+    im[: im.size // 2] = -1e-3
+    e_qp = float(s.eps[n]) - 0.8
+    t0 = time.perf_counter()
+    OC.spectral_cumulant(s.omega_real[c], im, float(s.eps[n]), e_qp, 0.1 / EV_PER_HA, 2 ** 18,
+                         0.01 / EV_PER_HA, 3500, e_qp - 30 / EV_PER_HA)
+    t_cum = time.perf_counter() - t0
+    del I
+
+    t_solve = t_imag / len(cores) + n_tasks_per_core * t_task + t_quad + t_cum
+    return {
+        "value": 1.0 / t_solve,
+        "unit": "solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"imaginary axis of all {len(cores)} cores ({t_imag:.1f} s), {done} residue "
+                   f"tasks ({t_task * 1e3:.0f} ms each), one 2^18-point cumulant ({t_cum:.1f} s); "
+                   f"extrapolated to {n_tasks_per_core:.0f} residue tasks per core-state solve"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", help="workload (default: the benzene-sized c2)")
+    ap.add_argument("--mode", default="full", choices=["full", "decoupled"])
+    ap.add_argument("--n-real", type=int, default=None,
+                    help="override the real grid size (a reduced run, not the named workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-tasks", type=int, default=24)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": 2 ** 30, "bytes_written": 2 ** 30,
+                          "launches": 3}))
+        return
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout "
+              "is a design note, not an implemented path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2412_17132_amd as gwc
+    from oracle import sigma as OS  # task count only (host bookkeeping)
+    from workloads import CONFIGS, EV_PER_HA, system_from_config
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cfg = CONFIGS[args.config]
+    over = {} if args.n_real is None else {"n_real": args.n_real}
+    s = system_from_config(cfg, **over)
+    d = gwc.to_device(s, dev)
+    n_core = s.n_core
+    n_t, d_omega = 2 ** 18, 0.01 / EV_PER_HA
+    n_out = 3500
+
+    def step():
+        out = gwc.gwc_sigma_core(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],
+                                 d["omega_imag"], d["w_imag"], d["omega_real"], d["eta"],
+                                 mode=args.mode)
+        e_qp = out["e_qp"].cpu().numpy()
+        spectra = []
+        for c in range(n_core):
+            n = int(s.core_idx[c])
+            A, z = gwc.gwc_spectral_cumulant(d["omega_real"][c], out["im_sigma_dec"][c],
+                                             float(s.eps[n]), float(e_qp[c]), s.eta, n_t, d_omega,
+                                             n_out, float(e_qp[c]) - 30 / EV_PER_HA)
+            spectra.append(A)
+        return out, spectra
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    gwc.timing_enable(True)
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pi = gwc.timing_get("pi_build_f64")
+    lu = gwc.timing_get("lu_bordered")
+    gwc.timing_enable(False)
+
+    solves = args.steps * n_core
+    value = solves / elapsed
+    n_tasks = OS.count_residue_tasks(s.eps, s.occ, s.core_idx, s.omega_real, args.mode)
+    launches = max(pi["launches"], 1)
+    achieved = pi["flops"] / (pi["total_ms"] / 1e3) / 1e12 if pi["total_ms"] > 0 else 0.0
+    tpl = _traffic_per_launch()
+    roofline = {
+        "bound": "mfma",
+        "achieved": achieved,
+        "peak": FP64_MFMA_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+        "traffic": tpl,
+        "kernel": "pi_build_f64",
+        "avg_launch_ms": pi["total_ms"] / launches,
+        "flops_per_launch": pi["flops"] / launches,
+    }
+    lu_achieved = lu["flops"] / (lu["total_ms"] / 1e3) / 1e12 if lu["total_ms"] > 0 else 0.0
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cfg.name}: {cfg.description}" + ("" if args.n_real is None else f" (n_real={args.n_real})"),
+            "n_basis": cfg.n_basis, "n_occ": cfg.n_occ, "n_core": n_core, "n_aux": cfg.n_aux,
+            "n_imag": cfg.n_imag, "n_real": s.omega_real.shape[1], "eta_ev": cfg.eta_ev,
+            "mode": args.mode, "precision": "fp64", "residue_tasks_per_step": n_tasks,
+            "cumulant_n_t": n_t, "parallelism": "single-gpu",
+        },
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "per": "step (all core states)"},
+        "roofline": roofline,
+        "kernels": {
+            "pi_build_f64": {"ms": pi["total_ms"], "launches": pi["launches"], "tflops": achieved},
+            "lu_bordered": {"ms": lu["total_ms"], "launches": lu["launches"], "tflops": lu_achieved},
+        },
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(s, args.mode, n_tasks / n_core, args.cpu_tasks)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

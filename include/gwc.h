@@ -165,6 +165,18 @@ typedef struct {
 int gwc_spectral_cumulant(const gwc_cumulant_args *args, double *A_out, double *z_out,
                           void *hip_stream);
 
+/* Kernel timing (diagnostics for profiling harnesses, not part of the method).
+ * gwc_timing_enable(1) clears the counters and, until gwc_timing_enable(0),
+ * brackets every launch of the named hot kernels with HIP events recorded on
+ * the stream the kernel runs on.  gwc_timing_get returns, for one kernel name
+ * ("pi_build_f64" or "lu_bordered"), the summed event time in ms, the number
+ * of launches and the algorithmic flop count of those launches (Pi build:
+ * 2 N_aux (N_aux + 1) N_ov per complex residue frequency, half that on the
+ * imaginary axis; LU: (8/3) N^3 + 8 N^2 R per bordered N x N matrix with R
+ * border vectors).  Returns GWC_ERR_INVALID_ARG for an unknown name. */
+int gwc_timing_enable(int on);
+int gwc_timing_get(const char *kernel, double *total_ms, long long *launches, double *flops);
+
 /* Message describing the last non-OK return on the calling thread ("" if none). */
 const char *gwc_last_error(void);
 

@@ -33,6 +33,8 @@ EXPORTED_SYMBOLS = (
     "gwc_spectral_cumulant",
     "gwc_last_error",
     "gwc_version",
+    "gwc_timing_enable",
+    "gwc_timing_get",
 )
 
 
@@ -99,6 +101,11 @@ def load(path: str = LIB_PATH):
     lib.gwc_last_error.restype = ctypes.c_char_p
     lib.gwc_version.argtypes = []
     lib.gwc_version.restype = c_int
+    lib.gwc_timing_enable.argtypes = [c_int]
+    lib.gwc_timing_enable.restype = c_int
+    lib.gwc_timing_get.argtypes = [ctypes.c_char_p, POINTER(c_double), POINTER(ctypes.c_longlong),
+                                   POINTER(c_double)]
+    lib.gwc_timing_get.restype = c_int
     _lib = lib
     return lib
 

@@ -134,5 +134,19 @@ def to_device(system, device="cuda"):
     )
 
 
+def timing_enable(on: bool = True) -> None:
+    """Clear and (de)activate the per-kernel event timing of libgwc."""
+    N.check(N.load().gwc_timing_enable(1 if on else 0))
+
+
+def timing_get(kernel: str) -> dict:
+    """Summed event time (ms), launch count and algorithmic flops of one kernel."""
+    import ctypes
+    ms, n, fl = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+    N.check(N.load().gwc_timing_get(kernel.encode(), ctypes.byref(ms), ctypes.byref(n),
+                                    ctypes.byref(fl)))
+    return {"total_ms": ms.value, "launches": n.value, "flops": fl.value}
+
+
 def version() -> int:
     return int(N.load().gwc_version())

@@ -28,6 +28,23 @@ namespace {
 thread_local std::string g_last_error;
 std::mutex g_mutex;
 
+// Kernel timing (diagnostics): event pairs recorded around hot launches on the
+// launch stream, resolved after the stream synchronises.
+struct TimerStat {
+  double total_ms = 0.0;
+  long long launches = 0;
+  double flops = 0.0;
+};
+struct PendingTiming {
+  int kernel;  // 0 = pi_build_f64, 1 = lu_bordered
+  hipEvent_t a, b;
+  double flops;
+};
+bool g_timing = false;
+TimerStat g_stats[2];
+std::vector<PendingTiming> g_pending;
+const char *const kTimedKernels[2] = {"pi_build_f64", "lu_bordered"};
+
 struct GwcError {
   int code;
   std::string msg;
@@ -49,6 +66,30 @@ struct GwcError {
       fail(e_ == hipErrorOutOfMemory ? GWC_ERR_OUT_OF_MEMORY : GWC_ERR_DEVICE, "%s: %s", #x, \
            hipGetErrorString(e_));                                                            \
   } while (0)
+
+hipEvent_t timing_mark(hipStream_t s) {
+  hipEvent_t e;
+  HIPCHECK(hipEventCreate(&e));
+  HIPCHECK(hipEventRecord(e, s));
+  return e;
+}
+
+// Folds the recorded event pairs into the counters (stream must be idle).
+void timing_resolve() {
+  for (auto &p : g_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_stats[p.kernel].total_ms += ms;
+      g_stats[p.kernel].launches += 1;
+      g_stats[p.kernel].flops += p.flops;
+    } else {
+      (void)hipGetLastError();
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  g_pending.clear();
+}
 
 // Device allocation owned for the duration of one call.
 struct DevBuf {
@@ -135,7 +176,7 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Bytes of device memory the batched matrices of one launch may use.
 size_t batch_budget_bytes() {
-  size_t budget = size_t(16) << 30;
+  size_t budget = size_t(48) << 30;
   if (const char *e = std::getenv("GWC_BATCH_BYTES")) {
     const long long v = std::atoll(e);
     if (v > 0) budget = (size_t)v;
@@ -149,7 +190,7 @@ size_t batch_budget_bytes() {
 }
 
 int max_batch_tasks() {
-  int f = 512;
+  int f = 1024;
   if (const char *e = std::getenv("GWC_MAX_BATCH")) {
     const int v = std::atoi(e);
     if (v > 0) f = v;
@@ -213,19 +254,32 @@ void run_screening(const Resident &rs, const TaskList &tl, int R, double2 *W_out
     const double2 *z = dz.as<double2>() + t0;
     gwc::launch_chi(rs.eps, rs.n_occ, rs.n_virt, z, Fb, rs.ldl, dchr.as<double>(),
                     dchi.as<double>(), s);
+    hipEvent_t ea = g_timing ? timing_mark(s) : nullptr;
     gwc::launch_pi_build_f64(rs.Lp, rs.ldl, N, dchr.as<double>(), dchi.as<double>(), Fb,
                              rs.tiles, rs.n_tiles, dG.as<double2>(), (long long)mat_elems, ldg, s);
+    if (g_timing) {
+      double fl = 0.0;
+      for (int t = 0; t < Fb; ++t) fl += (tl.z[t0 + t].x == 0.0 ? 1.0 : 2.0);
+      fl *= (double)N * (N + 1) * (double)rs.n_occ * rs.n_virt;
+      g_pending.push_back({0, ea, timing_mark(s), fl});
+    }
     gwc::launch_border(rs.M_oo, rs.M_ov, N, rs.n_occ, rs.n_virt, dn.as<int>() + t0,
                        dm.as<int>() + t0, Fb, R, dG.as<double2>(), (long long)mat_elems, ldg,
                        dbb.as<double>(), s);
+    hipEvent_t eb = g_timing ? timing_mark(s) : nullptr;
     gwc::launch_lu_bordered(dG.as<double2>(), (long long)mat_elems, ldg, N, R, Fb,
                             dbb.as<double>(), dob.as<long long>() + t0, dos.as<int>() + t0, W_out,
                             dst.as<int>() + t0, s);
+    if (g_timing) {
+      const double fl = Fb * ((8.0 / 3.0) * N * (double)N * N + 8.0 * (double)N * N * R);
+      g_pending.push_back({1, eb, timing_mark(s), fl});
+    }
     HIPCHECK(hipGetLastError());
   }
   std::vector<int> st(T);
   HIPCHECK(hipMemcpyAsync(st.data(), dst.p, T * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
+  timing_resolve();
   status_all.insert(status_all.end(), st.begin(), st.end());
 }
 
@@ -488,6 +542,33 @@ int gwc_sigma_core(const gwc_system *sys, const gwc_sigma_args *args, gwc_sigma_
 int gwc_spectral_cumulant(const gwc_cumulant_args *args, double *A_out, double *z_out,
                           void *hip_stream) {
   return guarded([&] { return spectral_cumulant_impl(args, A_out, z_out, (hipStream_t)hip_stream); });
+}
+
+int gwc_timing_enable(int on) {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  for (auto &p : g_pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  g_pending.clear();
+  g_stats[0] = TimerStat{};
+  g_stats[1] = TimerStat{};
+  g_timing = on != 0;
+  return GWC_OK;
+}
+
+int gwc_timing_get(const char *kernel, double *total_ms, long long *launches, double *flops) {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  if (!kernel) return GWC_ERR_INVALID_ARG;
+  for (int k = 0; k < 2; ++k) {
+    if (std::string(kernel) == kTimedKernels[k]) {
+      if (total_ms) *total_ms = g_stats[k].total_ms;
+      if (launches) *launches = g_stats[k].launches;
+      if (flops) *flops = g_stats[k].flops;
+      return GWC_OK;
+    }
+  }
+  return GWC_ERR_INVALID_ARG;
 }
 
 const char *gwc_last_error(void) { return g_last_error.c_str(); }
