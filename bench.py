@@ -36,9 +36,10 @@ def _sha(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def _traffic_per_launch():
-    """HBM bytes per Pi-build launch from the committed rocprofv3 PMC summary,
-    or None when absent or taken on a different kernel source."""
+def _traffic_per_task():
+    """HBM bytes per Pi-build frequency (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed rocprofv3 PMC summary, or None when absent or taken on
+    a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -46,7 +47,7 @@ def _traffic_per_launch():
         return None
     if t.get("kernel_source_sha256") != _sha(PI_SOURCE):
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_task")
 
 
 def cpu_baseline(system, mode, n_tasks_per_core, budget_tasks=24):
@@ -203,7 +204,9 @@ def main():
     n_tasks = OS.count_residue_tasks(s.eps, s.occ, s.core_idx, s.omega_real, args.mode)
     launches = max(pi["launches"], 1)
     achieved = pi["flops"] / (pi["total_ms"] / 1e3) / 1e12 if pi["total_ms"] > 0 else 0.0
-    tpl = _traffic_per_launch()
+    tpt = _traffic_per_task()
+    pi_tasks = args.steps * (len(s.omega_imag) * n_core + n_tasks)
+    tpl = None if tpt is None else tpt * pi_tasks / launches
     roofline = {
         "bound": "mfma",
         "achieved": achieved,

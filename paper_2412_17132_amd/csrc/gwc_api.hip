@@ -232,8 +232,11 @@ void run_screening(const Resident &rs, const TaskList &tl, int R, double2 *W_out
   if (fb < 1) fail(GWC_ERR_OUT_OF_MEMORY, "one %d x %d complex matrix (%zu bytes) exceeds the batch budget", n, n, mat_bytes);
   const int F = (int)fb;
 
-  DevBuf dG, dchr, dchi, dz, dn, dm, dob, dos, dbb, dst;
+  if (n > gwc::lu_max_order())
+    fail(GWC_ERR_UNSUPPORTED, "bordered order %d exceeds %d", n, gwc::lu_max_order());
+  DevBuf dG, dchr, dchi, dz, dn, dm, dob, dos, dbb, dst, dscr;
   dG.alloc(mat_bytes * F);
+  dscr.alloc(gwc::lu_scratch_bytes(F));
   dchr.alloc((size_t)F * rs.ldl * sizeof(double));
   dchi.alloc((size_t)F * rs.ldl * sizeof(double));
   dz.alloc(T * sizeof(double2));
@@ -269,7 +272,7 @@ void run_screening(const Resident &rs, const TaskList &tl, int R, double2 *W_out
     hipEvent_t eb = g_timing ? timing_mark(s) : nullptr;
     gwc::launch_lu_bordered(dG.as<double2>(), (long long)mat_elems, ldg, N, R, Fb,
                             dbb.as<double>(), dob.as<long long>() + t0, dos.as<int>() + t0, W_out,
-                            dst.as<int>() + t0, s);
+                            dst.as<int>() + t0, dscr.p, s);
     if (g_timing) {
       const double fl = Fb * ((8.0 / 3.0) * N * (double)N * N + 8.0 * (double)N * N * R);
       g_pending.push_back({1, eb, timing_mark(s), fl});

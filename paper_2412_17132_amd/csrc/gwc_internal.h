@@ -38,9 +38,13 @@ void launch_pi_build_f64(const double *Lp, int ldl, int n_aux, const double *chi
 void launch_border(const double *M_oo, const double *M_ov, int n_aux, int n_occ, int n_virt,
                    const int *task_n, const int *task_m, int F, int R, double2 *G,
                    long long g_stride, int ldg, double *bb, hipStream_t stream);
+// Batched bordered LU; `scratch` must hold lu_scratch_bytes(F) bytes.  Orders
+// up to lu_max_order() (= N + R) are supported.
+size_t lu_scratch_bytes(int F);
+int lu_max_order();
 void launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
                         const double *bb, const long long *out_base, const int *out_stride,
-                        double2 *W_out, int *status, hipStream_t stream);
+                        double2 *W_out, int *status, void *scratch, hipStream_t stream);
 
 void launch_sigma_x(const double *M_oo, int n_aux, int n_occ, const int *core_idx, int n_core,
                     double *sigma_x, hipStream_t stream);

@@ -1,6 +1,6 @@
 // Screened-interaction elements from a bordered LU factorisation (FP64 complex).
 //
-// For one frequency z and border vectors b_r (r < R) the workgroup factors
+// For one frequency z and border vectors b_r (r < R) the batch factors
 //
 //        [ 1 - Pi(z)   B ]          B = [b_0 ... b_{R-1}]   (N x R)
 //   M =  [ B^T         0 ]          n = N + R
@@ -15,24 +15,31 @@
 // Only the diagonal of the R x R border block is needed, so border-border
 // tiles away from the diagonal are skipped.
 //
-// Blocking (one workgroup per matrix, matrices private to a CU, so HBM
-// traffic of the trailing update is what bounds it):
-//   outer panels of LU_NBO = 64 columns, each factored as LU_NB = 16-wide inner
-//   blocks (column-by-column pivoting, rank-16 updates inside the panel only);
-//   then the panel's row swaps on the trailing columns, the 64 rows of U12 by
-//   a blocked unit-lower solve, and one rank-64 trailing update whose 64 x 64
-//   output tiles stay in registers across K = 64 (FP64 MFMA, the complex
-//   product as four real products).  The trailing matrix is read and written
-//   once per 64 eliminated columns.
+// Batched right-looking LU in steps of NBO = 64 columns, three launches per
+// step over all matrices of the batch:
+//   P  one workgroup per matrix: the 64-wide panel (rows K0..n) is factored in
+//      register-resident column blocks of width W (partial pivoting, rank-1
+//      updates in registers, pivot row broadcast through LDS), with the block
+//      updates inside the panel on MFMA; then the permutation of the step as a
+//      list of row moves, and L11^-1 (64 x 64 unit lower) for the next launch;
+//   S  one workgroup per (matrix, 16 trailing columns): applies the row moves
+//      and forms U12 = L11^-1 A12 on MFMA;
+//   G  one workgroup per (matrix, 64 x 64 trailing tile): A22 -= L21 U12 with
+//      K = 64 on MFMA (the complex product as four real products), tiles of a
+//      matrix kept on one XCD so its L21 / U12 panels stay in that L2.
 #include "gwc_internal.h"
 
 namespace gwc {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int NBO = 64;  // outer panel width
-constexpr int GT = 64;   // update tile
-constexpr int KCH = 16;  // K chunk staged in LDS
+constexpr int NBO = 64;                     // columns per step
+constexpr int PT = 512;                     // panel threads
+constexpr int PNW = PT / 64;
+constexpr int MAX_MOVES = 2 * NBO;
+constexpr int SW = 16;                      // trailing columns per swap/U12 workgroup
+constexpr int KCH = 16;                     // K chunk staged in LDS
+constexpr int NXCD = 8;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -50,30 +57,50 @@ __device__ __forceinline__ double2 cinv(double2 d) {
   return make_double2(r / den, -1.0 / den);
 }
 
-struct LuShared {
-  double red_v[LU_THREADS / 64];
-  int red_i[LU_THREADS / 64];
-  int piv[NBO];           // absolute pivot rows of the current outer panel
-  double2 prow[LU_NB];
-  double2 L11[LU_NB][LU_NB];
-  double2 Ls[GT][KCH + 1];
-  double2 Us[KCH][GT + 1];
-  int singular;
+// Workgroup -> (matrix, item) with all items of a matrix on one XCD
+// (workgroups are dispatched round-robin over the 8 XCDs).
+__device__ __forceinline__ bool xcd_map(int wg, int items, int F, int &f, int &item) {
+  const int x = wg % NXCD, j = wg / NXCD;
+  f = (j / items) * NXCD + x;
+  item = j - (j / items) * items;
+  return f < F;
+}
+
+// ===========================================================================
+// P: panel factorisation
+struct PanelShared {
+  double red_v[PNW];
+  int red_i[PNW];
+  int piv[NBO];
+  int mrow[MAX_MOVES], mcont[MAX_MOVES];
+  int flags;
+  double2 prow[16];
+  double2 xbuf[2][16];
+  double2 l16[16][16];
+  union {
+    struct {
+      double2 Ls[128][KCH + 1];
+      double2 Us[KCH][64 + 1];
+    } g;
+    struct {
+      double2 L11[NBO][NBO + 1];
+      double2 X[NBO][NBO + 1];
+    } inv;
+  } u;
 };
 
-// A[r0:r1, c0:c1] -= A[r0:r1, kA:kA+K] * A[kA:kA+K, c0:c1].  Tiles entirely
-// inside the border-border block and off its diagonal are skipped.
-__device__ void gemm_update(double2 *__restrict__ A, int ldg, int N, int r0, int r1, int c0,
-                            int c1, int kA, int K, LuShared &sh) {
+// A[r0:r1, c0:c1] -= A[r0:r1, kA:kA+K] A[kA:kA+K, c0:c1] (inside the panel;
+// 8 waves as 4 x 2 quadrants of a 128 x 64 tile).
+__device__ void panel_gemm(double2 *__restrict__ A, int ldg, int r0, int r1, int c0, int c1,
+                           int kA, int K, PanelShared &sh) {
   if (r1 <= r0 || c1 <= c0 || K <= 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int mt = (r1 - r0 + GT - 1) / GT, nt = (c1 - c0 + GT - 1) / GT;
+  const int mt = (r1 - r0 + 127) / 128, nt = (c1 - c0 + 63) / 64;
   for (int tile = 0; tile < mt * nt; ++tile) {
     const int ti = tile / nt, tj = tile - ti * nt;
-    const int ra = r0 + ti * GT, ca = c0 + tj * GT;
-    if (ra >= N && ca >= N && (ra + GT <= ca || ca + GT <= ra)) continue;
+    const int ra = r0 + ti * 128, ca = c0 + tj * 64;
     d4 cre[2][2], cim[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -91,26 +118,26 @@ __device__ void gemm_update(double2 *__restrict__ A, int ldg, int N, int r0, int
       }
     for (int kc = 0; kc < K; kc += KCH) {
       const int kw = min(KCH, K - kc);
-      for (int idx = tid; idx < GT * KCH; idx += LU_THREADS) {
+      for (int idx = tid; idx < 128 * KCH; idx += PT) {
         const int r = idx / KCH, t = idx - r * KCH;
-        sh.Ls[r][t] = (ra + r < r1 && t < kw) ? A[(long long)(ra + r) * ldg + kA + kc + t]
-                                              : make_double2(0.0, 0.0);
+        sh.u.g.Ls[r][t] = (ra + r < r1 && t < kw) ? A[(long long)(ra + r) * ldg + kA + kc + t]
+                                                  : make_double2(0.0, 0.0);
       }
-      for (int idx = tid; idx < KCH * GT; idx += LU_THREADS) {
-        const int t = idx / GT, j = idx - t * GT;
-        sh.Us[t][j] = (t < kw && ca + j < c1) ? A[(long long)(kA + kc + t) * ldg + ca + j]
-                                              : make_double2(0.0, 0.0);
+      for (int idx = tid; idx < KCH * 64; idx += PT) {
+        const int t = idx / 64, j = idx - t * 64;
+        sh.u.g.Us[t][j] = (t < kw && ca + j < c1) ? A[(long long)(kA + kc + t) * ldg + ca + j]
+                                                  : make_double2(0.0, 0.0);
       }
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < KCH; kk += 4) {
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-          const double2 lv = sh.Ls[wr + 16 * a + li][kk + lk];
+          const double2 lv = sh.u.g.Ls[wr + 16 * a + li][kk + lk];
           const double ar = -lv.x, ai = -lv.y;
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
-            const double2 uv = sh.Us[kk + lk][wc + 16 * b + li];
+            const double2 uv = sh.u.g.Us[kk + lk][wc + 16 * b + li];
             cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.x, cre[a][b], 0, 0, 0);
             cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, uv.y, cre[a][b], 0, 0, 0);
             cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.y, cim[a][b], 0, 0, 0);
@@ -136,32 +163,29 @@ __device__ void gemm_update(double2 *__restrict__ A, int ldg, int N, int r0, int
 }
 
 // Rows [k0, k0+kb) of columns [c0, c1): unit-lower solve with the kb x kb
-// diagonal block A[k0.., k0..].
-__device__ void trsm_block(double2 *__restrict__ A, int ldg, int k0, int kb, int c0, int c1,
-                           LuShared &sh) {
+// diagonal block.
+__device__ void panel_trsm(double2 *__restrict__ A, int ldg, int k0, int kb, int c0, int c1,
+                           PanelShared &sh) {
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < LU_NB * LU_NB; idx += LU_THREADS) {
-    const int i = idx / LU_NB, t = idx - i * LU_NB;
-    sh.L11[i][t] = (i < kb && t < kb) ? A[(long long)(k0 + i) * ldg + k0 + t] : make_double2(0.0, 0.0);
+  for (int idx = tid; idx < 16 * 16; idx += PT) {
+    const int i = idx / 16, t = idx - i * 16;
+    sh.l16[i][t] = (i < kb && t < kb) ? A[(long long)(k0 + i) * ldg + k0 + t] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  for (int j = c0 + tid; j < c1; j += LU_THREADS) {
-    // earlier rows are re-read from the cache (this thread wrote them)
+  for (int j = c0 + tid; j < c1; j += PT) {
     for (int i = 1; i < kb; ++i) {
       double2 acc = A[(long long)(k0 + i) * ldg + j];
-      for (int t = 0; t < i; ++t) acc = csub(acc, cmul(sh.L11[i][t], A[(long long)(k0 + t) * ldg + j]));
+      for (int t = 0; t < i; ++t) acc = csub(acc, cmul(sh.l16[i][t], A[(long long)(k0 + t) * ldg + j]));
       A[(long long)(k0 + i) * ldg + j] = acc;
     }
   }
   __syncthreads();
 }
 
-// Row interchanges (row_base + t) <-> piv[t0 + t] for t < cnt, in order, on
-// columns [c0, c1).  Each thread owns whole columns, so no barrier is needed
-// between interchanges.
-__device__ void apply_swaps(double2 *__restrict__ A, int ldg, int row_base, int t0, int cnt,
-                            int c0, int c1, const LuShared &sh) {
-  for (int j = c0 + threadIdx.x; j < c1; j += LU_THREADS) {
+// Interchanges (row_base + t) <-> piv[t0 + t], t < cnt, in order, on [c0, c1).
+__device__ void panel_swaps(double2 *__restrict__ A, int ldg, int row_base, int t0, int cnt,
+                            int c0, int c1, const PanelShared &sh) {
+  for (int j = c0 + threadIdx.x; j < c1; j += PT) {
     for (int t = 0; t < cnt; ++t) {
       const int c = row_base + t, p = sh.piv[t0 + t];
       if (p != c) {
@@ -175,120 +199,391 @@ __device__ void apply_swaps(double2 *__restrict__ A, int ldg, int row_base, int 
   }
 }
 
-__global__ void __launch_bounds__(LU_THREADS, 4)
-lu_bordered_kernel(double2 *__restrict__ G, long long g_stride, int ldg, int N, int R,
-                   const double *__restrict__ bb, const long long *__restrict__ out_base,
-                   const int *__restrict__ out_stride, double2 *__restrict__ W_out,
-                   int *__restrict__ status) {
-  constexpr int NT = LU_THREADS, NW = LU_THREADS / 64;
-  __shared__ LuShared sh;
+template <int RPT, int W>
+__global__ void __launch_bounds__(PT, 1)
+lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0,
+                int *__restrict__ piv_g, int *__restrict__ moves_g, double2 *__restrict__ linv_g,
+                int *__restrict__ status) {
+  __shared__ PanelShared sh;
   const int f = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = N + R;
-  double2 *A = G + (long long)f * g_stride;
-  if (tid == 0) sh.singular = 0;
+  double2 *A = G + (long long)f * gs;
+  const int kbo = min(NBO, N - K0), kend = K0 + kbo;
+  if (tid == 0) sh.flags = 0;
+  __syncthreads();
 
-  for (int K0 = 0; K0 < N; K0 += NBO) {
-    const int kbo = min(NBO, N - K0);
-    const int kend = K0 + kbo;
-
-    // ---- outer panel: inner blocks of LU_NB columns
-    for (int k0 = K0; k0 < kend; k0 += LU_NB) {
-      const int kb = min(LU_NB, kend - k0);
-      const int ke = k0 + kb;
-      for (int c = k0; c < ke; ++c) {
-        double best = -1.0;
-        int bi = c;
-        for (int r = c + tid; r < N; r += NT) {
-          const double2 v = A[(long long)r * ldg + c];
-          const double m = fabs(v.x) + fabs(v.y);
+  for (int k0 = K0; k0 < kend; k0 += W) {
+    const int kb = min(W, kend - k0), ke = k0 + kb;
+    double2 v[RPT][W];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int r = k0 + tid + s * PT;
+#pragma unroll
+      for (int j = 0; j < W; ++j)
+        v[s][j] = (r < n && j < kb) ? A[(long long)r * ldg + k0 + j] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      if (c < kb) {
+      const int rc = k0 + c;
+      double best = -1.0;
+      int bi = rc;
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const int r = k0 + tid + s * PT;
+        if (r >= rc && r < N) {
+          const double m = fabs(v[s][c].x) + fabs(v[s][c].y);
           if (m > best) { best = m; bi = r; }
         }
+      }
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ob = __shfl_xor(best, off);
-          const int oi = __shfl_xor(bi, off);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        if (lane == 0) { sh.red_v[wave] = best; sh.red_i[wave] = bi; }
-        __syncthreads();
-        if (tid == 0) {
-          double b = sh.red_v[0];
-          int p = sh.red_i[0];
-          for (int w = 1; w < NW; ++w)
-            if (sh.red_v[w] > b || (sh.red_v[w] == b && sh.red_i[w] < p)) { b = sh.red_v[w]; p = sh.red_i[w]; }
-          sh.piv[c - K0] = p;
-        }
-        __syncthreads();
-        const int p = sh.piv[c - K0];
-        if (p != c && tid < kb) {
-          double2 *rc = A + (long long)c * ldg + k0 + tid;
-          double2 *rp = A + (long long)p * ldg + k0 + tid;
-          const double2 t = *rc;
-          *rc = *rp;
-          *rp = t;
-        }
-        __syncthreads();
-        if (tid < kb) sh.prow[tid] = A[(long long)c * ldg + k0 + tid];
-        __syncthreads();
-        const double2 d = sh.prow[c - k0];
-        double2 inv;
-        if (d.x == 0.0 && d.y == 0.0) {
-          if (tid == 0) sh.singular = 1;
-          inv = make_double2(0.0, 0.0);
-        } else {
-          inv = cinv(d);
-        }
-        for (int r = c + 1 + tid; r < n; r += NT) {
-          double2 *row = A + (long long)r * ldg;
-          const double2 l = cmul(row[c], inv);
-          row[c] = l;
-          for (int j = c + 1; j < ke; ++j) row[j] = csub(row[j], cmul(l, sh.prow[j - k0]));
-        }
-        __syncthreads();
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
-      // this block's interchanges on the rest of the outer panel
-      apply_swaps(A, ldg, k0, k0 - K0, kb, K0, k0, sh);
-      apply_swaps(A, ldg, k0, k0 - K0, kb, ke, kend, sh);
+      if (lane == 0) { sh.red_v[wave] = best; sh.red_i[wave] = bi; }
       __syncthreads();
-      if (ke < kend) {
-        trsm_block(A, ldg, k0, kb, ke, kend, sh);
-        gemm_update(A, ldg, N, ke, n, ke, kend, k0, kb, sh);
+      if (tid == 0) {
+        double b = sh.red_v[0];
+        int p = sh.red_i[0];
+        for (int w = 1; w < PNW; ++w)
+          if (sh.red_v[w] > b || (sh.red_v[w] == b && sh.red_i[w] < p)) { b = sh.red_v[w]; p = sh.red_i[w]; }
+        sh.piv[rc - K0] = p;
       }
       __syncthreads();
-    }
-    if (kend >= n) continue;
-
-    // ---- the panel's interchanges on the trailing columns
-    apply_swaps(A, ldg, K0, 0, kbo, kend, n, sh);
-    __syncthreads();
-    // ---- U12 rows [K0, kend): blocked unit-lower solve
-    for (int k0 = K0; k0 < kend; k0 += LU_NB) {
-      const int kb = min(LU_NB, kend - k0);
-      gemm_update(A, ldg, N, k0, k0 + kb, kend, n, K0, k0 - K0, sh);
+      const int p = sh.piv[rc - K0];
+      if (p != rc) {
+        // row rc lives in slot 0 of thread c, row p in slot sp of thread tp
+        const int tp = (p - k0) % PT, sp = (p - k0) / PT;
+        if (tid == tp) {
+#pragma unroll
+          for (int s = 0; s < RPT; ++s)
+            if (s == sp) {
+#pragma unroll
+              for (int j = 0; j < W; ++j) sh.xbuf[0][j] = v[s][j];
+            }
+        }
+        if (tid == c) {
+#pragma unroll
+          for (int j = 0; j < W; ++j) sh.xbuf[1][j] = v[0][j];
+        }
+        __syncthreads();
+        if (tid == c) {
+#pragma unroll
+          for (int j = 0; j < W; ++j) v[0][j] = sh.xbuf[0][j];
+        }
+        if (tid == tp) {
+#pragma unroll
+          for (int s = 0; s < RPT; ++s)
+            if (s == sp) {
+#pragma unroll
+              for (int j = 0; j < W; ++j) v[s][j] = sh.xbuf[1][j];
+            }
+        }
+      }
+      if (tid == c) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) sh.prow[j] = v[0][j];
+      }
       __syncthreads();
-      trsm_block(A, ldg, k0, kb, kend, n, sh);
+      const double2 d = sh.prow[c];
+      double2 inv;
+      if (d.x == 0.0 && d.y == 0.0) {
+        if (tid == 0) sh.flags = 1;
+        inv = make_double2(0.0, 0.0);
+      } else {
+        inv = cinv(d);
+      }
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const int r = k0 + tid + s * PT;
+        if (r > rc && r < n) {
+          const double2 l = cmul(v[s][c], inv);
+          v[s][c] = l;
+#pragma unroll
+          for (int j = c + 1; j < W; ++j)
+            if (j < kb) v[s][j] = csub(v[s][j], cmul(l, sh.prow[j]));
+        }
+      }
+      }  // c < kb
     }
-    // ---- rank-kbo trailing update
-    gemm_update(A, ldg, N, kend, n, kend, n, K0, kbo, sh);
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int r = k0 + tid + s * PT;
+      if (r < n) {
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+          if (j < kb) A[(long long)r * ldg + k0 + j] = v[s][j];
+      }
+    }
     __syncthreads();
+    // this block's interchanges on the rest of the panel
+    panel_swaps(A, ldg, k0, k0 - K0, kb, K0, k0, sh);
+    panel_swaps(A, ldg, k0, k0 - K0, kb, ke, kend, sh);
+    __syncthreads();
+    if (ke < kend) {
+      panel_trsm(A, ldg, k0, kb, ke, kend, sh);
+      panel_gemm(A, ldg, ke, n, ke, kend, k0, kb, sh);
+      __syncthreads();
+    }
   }
 
-  // ---- W_r = -S_rr - b_r^T b_r
-  for (int r = tid; r < R; r += NT) {
+  if (tid < kbo) piv_g[(long long)f * NBO + tid] = sh.piv[tid];
+  // net row moves of the step: rows K0..kend plus the rows they swapped with
+  if (tid == 0) {
+    int cnt = kbo;
+    for (int t = 0; t < kbo; ++t) { sh.mrow[t] = K0 + t; sh.mcont[t] = K0 + t; }
+    for (int t = 0; t < kbo; ++t) {
+      const int p = sh.piv[t];
+      const int a = t;
+      int b;
+      if (p < kend) {
+        b = p - K0;
+      } else {
+        b = -1;
+        for (int i = kbo; i < cnt; ++i)
+          if (sh.mrow[i] == p) { b = i; break; }
+        if (b < 0) { b = cnt; sh.mrow[cnt] = p; sh.mcont[cnt] = p; ++cnt; }
+      }
+      const int tmp = sh.mcont[a];
+      sh.mcont[a] = sh.mcont[b];
+      sh.mcont[b] = tmp;
+    }
+    int m = 0;
+    int *mv = moves_g + (long long)f * (1 + 2 * MAX_MOVES);
+    for (int i = 0; i < cnt; ++i)
+      if (sh.mcont[i] != sh.mrow[i]) {
+        mv[1 + 2 * m] = sh.mrow[i];
+        mv[2 + 2 * m] = sh.mcont[i];
+        ++m;
+      }
+    mv[0] = m;
+    if (sh.flags) status[f] = 1;
+  }
+  __syncthreads();
+  // L11^-1 (unit lower): column j = tid by forward substitution in LDS
+  for (int idx = tid; idx < NBO * NBO; idx += PT) {
+    const int i = idx / NBO, t = idx - i * NBO;
+    sh.u.inv.L11[i][t] = (i < kbo && t < i) ? A[(long long)(K0 + i) * ldg + K0 + t] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (tid < NBO) {
+    const int j = tid;
+    for (int i = 0; i < NBO; ++i) {
+      double2 x = make_double2(i == j ? 1.0 : 0.0, 0.0);
+      if (i > j && i < kbo) {
+        for (int t = j; t < i; ++t) x = csub(x, cmul(sh.u.inv.L11[i][t], sh.u.inv.X[t][j]));
+      } else if (i >= kbo) {
+        x = make_double2(0.0, 0.0);
+      }
+      sh.u.inv.X[i][j] = x;
+    }
+  }
+  __syncthreads();
+  double2 *Li = linv_g + (long long)f * NBO * NBO;
+  for (int idx = tid; idx < NBO * NBO; idx += PT) {
+    const int i = idx / NBO, j = idx - i * NBO;
+    Li[idx] = (i < kbo && j < kbo) ? sh.u.inv.X[i][j] : make_double2(0.0, 0.0);
+  }
+}
+
+// ===========================================================================
+// S: row moves on the trailing columns and U12 = L11^-1 A12 (16 columns per
+// workgroup, 4 waves of 16 rows each).
+__global__ void __launch_bounds__(256)
+lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0, int F,
+                   int nchunks, const int *__restrict__ moves_g,
+                   const double2 *__restrict__ linv_g) {
+  __shared__ int mv[1 + 2 * MAX_MOVES];
+  __shared__ double2 val[MAX_MOVES][SW + 1];
+  int f, chunk;
+  if (!xcd_map(blockIdx.x, nchunks, F, f, chunk)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int n = N + R;
+  const int kbo = min(NBO, N - K0), kend = K0 + kbo;
+  const int c0 = kend + chunk * SW, cw = min(SW, n - c0);
+  double2 *A = G + (long long)f * gs;
+  const int *m = moves_g + (long long)f * (1 + 2 * MAX_MOVES);
+  for (int i = tid; i < 1 + 2 * MAX_MOVES; i += 256) mv[i] = m[i];
+  __syncthreads();
+  const int cnt = mv[0];
+  for (int idx = tid; idx < cnt * SW; idx += 256) {
+    const int i = idx / SW, j = idx - i * SW;
+    val[i][j] = (j < cw) ? A[(long long)mv[2 + 2 * i] * ldg + c0 + j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < cnt * SW; idx += 256) {
+    const int i = idx / SW, j = idx - i * SW;
+    if (j < cw) A[(long long)mv[1 + 2 * i] * ldg + c0 + j] = val[i][j];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < NBO * SW; idx += 256) {
+    const int t = idx / SW, j = idx - t * SW;
+    val[t][j] = (t < kbo && j < cw) ? A[(long long)(K0 + t) * ldg + c0 + j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const double2 *Li = linv_g + (long long)f * NBO * NBO;
+  d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int kk = 0; kk < NBO; kk += 4) {
+    const double2 a = Li[(16 * wave + li) * NBO + kk + lk];
+    const double2 b = val[kk + lk][li];
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * wave + 4 * r + lk;
+    if (row < kbo && li < cw) A[(long long)(K0 + row) * ldg + c0 + li] = make_double2(re[r], im[r]);
+  }
+}
+
+// ===========================================================================
+// G: trailing update A22 -= L21 U12, one 64 x 64 tile per workgroup.
+__global__ void __launch_bounds__(256, 4)
+lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0, int F,
+                   int mt) {
+  __shared__ double2 Ls[64][KCH + 1];
+  __shared__ double2 Us[KCH][64 + 1];
+  int f, tile;
+  if (!xcd_map(blockIdx.x, mt * mt, F, f, tile)) return;
+  const int n = N + R;
+  const int kbo = min(NBO, N - K0), kend = K0 + kbo;
+  const int ti = tile / mt, tj = tile - ti * mt;
+  const int ra = kend + ti * 64, ca = kend + tj * 64;
+  if (ra >= N && ca >= N && (ra + 64 <= ca || ca + 64 <= ra)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  double2 *A = G + (long long)f * gs;
+
+  d4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = ca + wc + 16 * b + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = ra + wr + 16 * a + 4 * r + lk;
+        double2 v = make_double2(0.0, 0.0);
+        if (row < n && col < n) v = A[(long long)row * ldg + col];
+        cre[a][b][r] = v.x;
+        cim[a][b][r] = v.y;
+      }
+    }
+  for (int kc = 0; kc < kbo; kc += KCH) {
+    const int kw = min(KCH, kbo - kc);
+#pragma unroll
+    for (int it = 0; it < (64 * KCH) / 256; ++it) {
+      const int idx = it * 256 + tid;
+      const int r = idx / KCH, t = idx - r * KCH;
+      Ls[r][t] = (ra + r < n && t < kw) ? A[(long long)(ra + r) * ldg + K0 + kc + t]
+                                        : make_double2(0.0, 0.0);
+      const int t2 = idx / 64, j = idx - t2 * 64;
+      Us[t2][j] = (t2 < kw && ca + j < n) ? A[(long long)(K0 + kc + t2) * ldg + ca + j]
+                                          : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KCH; kk += 4) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const double2 lv = Ls[wr + 16 * a + li][kk + lk];
+        const double ar = -lv.x, ai = -lv.y;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const double2 uv = Us[kk + lk][wc + 16 * b + li];
+          cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.x, cre[a][b], 0, 0, 0);
+          cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, uv.y, cre[a][b], 0, 0, 0);
+          cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.y, cim[a][b], 0, 0, 0);
+          cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, uv.x, cim[a][b], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = ca + wc + 16 * b + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = ra + wr + 16 * a + 4 * r + lk;
+        if (row < n && col < n) A[(long long)row * ldg + col] = make_double2(cre[a][b][r], cim[a][b][r]);
+      }
+    }
+}
+
+// ===========================================================================
+__global__ void lu_finish_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N,
+                                 int R, const double *__restrict__ bb,
+                                 const long long *__restrict__ out_base,
+                                 const int *__restrict__ out_stride, double2 *__restrict__ W_out) {
+  const int f = blockIdx.x;
+  const double2 *A = G + (long long)f * gs;
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
     const double2 s = A[(long long)(N + r) * ldg + N + r];
     W_out[out_base[f] + (long long)r * out_stride[f]] =
         make_double2(-s.x - bb[(long long)f * R + r], -s.y);
   }
-  __syncthreads();
-  if (tid == 0) status[f] = sh.singular;
+}
+
+__global__ void zero_int_kernel(int *__restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
+size_t lu_scratch_bytes(int F) {
+  return (size_t)F * (NBO * sizeof(int) + (1 + 2 * MAX_MOVES) * sizeof(int) +
+                      NBO * NBO * sizeof(double2)) + 256;
+}
+
+int lu_max_order() { return 24 * PT; }
+
+template <int RPT, int W>
+static void launch_panel(int F, double2 *G, long long gs, int ldg, int N, int R, int K0, int *piv,
+                         int *moves, double2 *linv, int *status, hipStream_t stream) {
+  lu_panel_kernel<RPT, W><<<F, PT, 0, stream>>>(G, gs, ldg, N, R, K0, piv, moves, linv, status);
 }
 
 void launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
                         const double *bb, const long long *out_base, const int *out_stride,
-                        double2 *W_out, int *status, hipStream_t stream) {
-  lu_bordered_kernel<<<F, LU_THREADS, 0, stream>>>(G, g_stride, ldg, N, R, bb, out_base,
-                                                   out_stride, W_out, status);
+                        double2 *W_out, int *status, void *scratch, hipStream_t stream) {
+  const int n = N + R;
+  int *piv = static_cast<int *>(scratch);
+  int *moves = piv + (size_t)F * NBO;
+  double2 *linv = reinterpret_cast<double2 *>(
+      (reinterpret_cast<uintptr_t>(moves + (size_t)F * (1 + 2 * MAX_MOVES)) + 255) & ~uintptr_t(255));
+  zero_int_kernel<<<(F + 255) / 256, 256, 0, stream>>>(status, F);
+  const int rpt = (n + PT - 1) / PT;
+  const int fgroups = (F + NXCD - 1) / NXCD;
+  for (int K0 = 0; K0 < N; K0 += NBO) {
+    const int kend = min(K0 + NBO, N);
+    if (rpt <= 1) launch_panel<1, 16>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    else if (rpt <= 2) launch_panel<2, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    else if (rpt <= 3) launch_panel<3, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    else if (rpt <= 4) launch_panel<4, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    else if (rpt <= 6) launch_panel<6, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    else if (rpt <= 8) launch_panel<8, 4>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    else if (rpt <= 12) launch_panel<12, 2>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    else if (rpt <= 16) launch_panel<16, 2>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    else launch_panel<24, 1>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    const int rem = n - kend;  // >= R >= 1
+    const int nch = (rem + SW - 1) / SW;
+    lu_swap_u12_kernel<<<NXCD * fgroups * nch, 256, 0, stream>>>(G, g_stride, ldg, N, R, K0, F,
+                                                                   nch, moves, linv);
+    const int mt = (rem + 63) / 64;
+    lu_trailing_kernel<<<NXCD * fgroups * mt * mt, 256, 0, stream>>>(G, g_stride, ldg, N, R, K0,
+                                                                      F, mt);
+  }
+  lu_finish_kernel<<<F, 64, 0, stream>>>(G, g_stride, ldg, N, R, bb, out_base, out_stride, W_out);
 }
 
 }  // namespace gwc
