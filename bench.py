@@ -120,6 +120,29 @@ def cpu_baseline(system, mode, n_tasks_per_core, budget_tasks=24):
     }
 
 
+def _satellites(w, A, e_qp, Z, eta, min_sep_ev=0.5, rel_height=0.05):
+    """Satellite peaks: local maxima of A - Z L_eta(w - E_QP) more than 0.5 eV
+    below E_QP with height >= 5 % of that remainder's maximum there, refined by
+    a parabola (the paper's criterion is in its SI, which is not available)."""
+    import numpy as np
+    from workloads import EV_PER_HA
+    A = A - Z * (eta / np.pi) / ((w - e_qp) ** 2 + eta * eta)
+    region = w < e_qp - min_sep_ev / EV_PER_HA
+    if not np.any(region):
+        return []
+    top = np.max(A[region])
+    idx = np.where((A[1:-1] > A[:-2]) & (A[1:-1] >= A[2:]))[0] + 1
+    out = []
+    for i in idx:
+        if not region[i] or A[i] < rel_height * top:
+            continue
+        y0, y1, y2 = A[i - 1], A[i], A[i + 1]
+        den = y0 - 2 * y1 + y2
+        dx = 0.5 * (y0 - y2) / den if den != 0 else 0.0
+        out.append(w[i] + dx * (w[i + 1] - w[i]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +152,11 @@ def main():
     ap.add_argument("--mode", default="full", choices=["full", "decoupled"])
     ap.add_argument("--n-real", type=int, default=None,
                     help="override the real grid size (a reduced run, not the named workload)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "bf16x3", "fp16x3"],
+                    help="precision of the timed path (default FP64)")
+    ap.add_argument("--compare", default="bf16x3", choices=["none", "bf16x3", "fp16x3"],
+                    help="also time this mixed-precision form and report its speed-up and its "
+                         "E_QP / satellite-position errors against the FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tasks", type=int, default=24)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -168,10 +196,10 @@ def main():
     n_t, d_omega = 2 ** 18, 0.01 / EV_PER_HA
     n_out = 3500
 
-    def step():
+    def step(precision=args.precision):
         out = gwc.gwc_sigma_core(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],
                                  d["omega_imag"], d["w_imag"], d["omega_real"], d["eta"],
-                                 mode=args.mode)
+                                 mode=args.mode, precision=precision)
         e_qp = out["e_qp"].cpu().numpy()
         spectra = []
         for c in range(n_core):
@@ -179,7 +207,7 @@ def main():
             A, z = gwc.gwc_spectral_cumulant(d["omega_real"][c], out["im_sigma_dec"][c],
                                              float(s.eps[n]), float(e_qp[c]), s.eta, n_t, d_omega,
                                              n_out, float(e_qp[c]) - 30 / EV_PER_HA)
-            spectra.append(A)
+            spectra.append((A, z))
         return out, spectra
 
     for _ in range(args.warmup):
@@ -190,12 +218,12 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        step()
+        last = step()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    pi = gwc.timing_get("pi_build_f64")
+    pi = gwc.timing_get("pi_build_f64" if args.precision == "fp64" else "pi_build_mixed")
     lu = gwc.timing_get("lu_bordered")
     gwc.timing_enable(False)
 
@@ -207,12 +235,16 @@ def main():
     tpt = _traffic_per_task()
     pi_tasks = args.steps * (len(s.omega_imag) * n_core + n_tasks)
     tpl = None if tpt is None else tpt * pi_tasks / launches
+    peak = FP64_MFMA_PEAK_TFLOPS
+    if args.precision != "fp64":
+        # three 16-bit MFMA products per algorithmic multiply-add; dense 16-bit peak
+        achieved, peak, tpl = 3.0 * achieved, 2500.0, None
     roofline = {
         "bound": "mfma",
         "achieved": achieved,
-        "peak": FP64_MFMA_PEAK_TFLOPS,
+        "peak": peak,
         "unit": "TFLOP/s",
-        "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+        "frac": achieved / peak,
         "traffic": tpl,
         "kernel": "pi_build_f64",
         "avg_launch_ms": pi["total_ms"] / launches,
@@ -230,13 +262,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else args.precision,
         "data": "synthetic",
         "config": {
             "workload": f"{cfg.name}: {cfg.description}" + ("" if args.n_real is None else f" (n_real={args.n_real})"),
             "n_basis": cfg.n_basis, "n_occ": cfg.n_occ, "n_core": n_core, "n_aux": cfg.n_aux,
             "n_imag": cfg.n_imag, "n_real": s.omega_real.shape[1], "eta_ev": cfg.eta_ev,
-            "mode": args.mode, "precision": "fp64", "residue_tasks_per_step": n_tasks,
+            "mode": args.mode, "precision": args.precision, "residue_tasks_per_step": n_tasks,
             "cumulant_n_t": n_t, "parallelism": "single-gpu",
         },
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -247,6 +279,50 @@ def main():
             "lu_bordered": {"ms": lu["total_ms"], "launches": lu["launches"], "tflops": lu_achieved},
         },
     }
+    if args.compare != "none" and args.precision == "fp64":
+        step(args.compare)  # warm-up of the mixed form
+        torch.cuda.synchronize()
+        gwc.timing_enable(True)
+        tm = time.perf_counter()
+        for _ in range(args.steps):
+            mixed = step(args.compare)
+        torch.cuda.synchronize()
+        el_m = time.perf_counter() - tm
+        pim = gwc.timing_get("pi_build_mixed")
+        gwc.timing_enable(False)
+        ref_out, ref_spec = last
+        mx_out, mx_spec = mixed
+        deq = np.abs(mx_out["e_qp"].cpu().numpy() - ref_out["e_qp"].cpu().numpy())
+        w_axis = None
+        worst = 0.0
+        for c in range(n_core):
+            eq_r = float(ref_out["e_qp"][c]); eq_m = float(mx_out["e_qp"][c])
+            wr = eq_r - 30 / EV_PER_HA + np.arange(n_out) * d_omega
+            wm = eq_m - 30 / EV_PER_HA + np.arange(n_out) * d_omega
+            pr = _satellites(wr, ref_spec[c][0].cpu().numpy(), eq_r, float(ref_spec[c][1][0]), s.eta)
+            pm = _satellites(wm, mx_spec[c][0].cpu().numpy(), eq_m, float(mx_spec[c][1][0]), s.eta)
+            for p in pr:
+                if pm:
+                    worst = max(worst, float(np.min(np.abs(np.asarray(pm) - p))))
+        sc_err = None
+        if args.mode == "full":
+            a = ref_out["sigma_c"].cpu().numpy(); b = mx_out["sigma_c"].cpu().numpy()
+            rel = np.abs((b - a)[..., 0] + 1j * (b - a)[..., 1]) / np.max(np.abs(a[..., 0] + 1j * a[..., 1]))
+            sc_err = {"max": float(rel.max()), "median": float(np.median(rel))}
+        pim_tf = pim["flops"] / (pim["total_ms"] / 1e3) / 1e12 if pim["total_ms"] > 0 else 0.0
+        res["mixed"] = {
+            "precision": args.compare,
+            "value": solves / el_m,
+            "ms_per_step": el_m / args.steps * 1e3,
+            "speedup_vs_fp64": elapsed / el_m,
+            "pi_build_ms": pim["total_ms"],
+            "pi_build_algorithmic_tflops": pim_tf,
+            "pi_build_mfma_tflops": 3.0 * pim_tf,
+            "pi_build_mfma_frac_of_2500": 3.0 * pim_tf / 2500.0,
+            "e_qp_max_err_mev": float(deq.max() * EV_PER_HA * 1e3),
+            "satellite_max_shift_mev": worst * EV_PER_HA * 1e3,
+            "sigma_c_rel_err": sc_err,
+        }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(s, args.mode, n_tasks / n_core, args.cpu_tasks)
     print(json.dumps(res), flush=True)

@@ -56,8 +56,8 @@ enum gwc_mode {
 enum gwc_precision {
   GWC_PREC_FP64 = 0,   /* everything in float64 */
   GWC_PREC_BF16X3 = 1, /* Pi build as hi*hi + hi*lo + lo*hi bf16 products, fp32 accumulation */
-  GWC_PREC_FP16X3 = 2, /* same with fp16 and power-of-two scaling */
-  GWC_PREC_FP8 = 3     /* reserved */
+  GWC_PREC_FP16X3 = 2, /* same with fp16 and power-of-two column and frequency scaling */
+  GWC_PREC_FP8 = 3     /* reserved: returns GWC_ERR_UNSUPPORTED */
 };
 
 /* A closed-shell system in the RI representation.
@@ -85,7 +85,9 @@ typedef struct {
  *   omega_real [n_core][n_real]  real frequencies per core state, strictly increasing
  *   eta        > 0               broadening of the residue arguments |eps_m - w| + i eta
  *   vxc        [n_core] or NULL  <n|v_xc|n>, NULL means 0
- *   mode       enum gwc_mode; precision enum gwc_precision */
+ *   mode       enum gwc_mode
+ *   precision  enum gwc_precision: the Pi builds (both axes) in that form; chi(z),
+ *              the LU of 1 - Pi, the residue sums and E_QP stay FP64 */
 typedef struct {
   int32_t n_core;
   const int32_t *core_idx;
@@ -169,10 +171,10 @@ int gwc_spectral_cumulant(const gwc_cumulant_args *args, double *A_out, double *
  * gwc_timing_enable(1) clears the counters and, until gwc_timing_enable(0),
  * brackets every launch of the named hot kernels with HIP events recorded on
  * the stream the kernel runs on.  gwc_timing_get returns, for one kernel name
- * ("pi_build_f64" or "lu_bordered"), the summed event time in ms, the number
- * of launches and the algorithmic flop count of those launches (Pi build:
- * 2 N_aux (N_aux + 1) N_ov per complex residue frequency, half that on the
- * imaginary axis; LU: (8/3) N^3 + 8 N^2 R per bordered N x N matrix with R
+ * ("pi_build_f64", "pi_build_mixed" or "lu_bordered"), the summed event time in ms, the number
+ * of launches and the algorithmic flop count of those launches (Pi build, in
+ * either precision: 2 N_aux (N_aux + 1) N_ov per complex residue frequency,
+ * half that on the imaginary axis; LU: (8/3) N^3 + 8 N^2 R per bordered N x N matrix with R
  * border vectors).  Returns GWC_ERR_INVALID_ARG for an unknown name. */
 int gwc_timing_enable(int on);
 int gwc_timing_get(const char *kernel, double *total_ms, long long *launches, double *flops);

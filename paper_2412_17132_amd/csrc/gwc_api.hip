@@ -36,14 +36,15 @@ struct TimerStat {
   double flops = 0.0;
 };
 struct PendingTiming {
-  int kernel;  // 0 = pi_build_f64, 1 = lu_bordered
+  int kernel;  // index into kTimedKernels
   hipEvent_t a, b;
   double flops;
 };
 bool g_timing = false;
-TimerStat g_stats[2];
+constexpr int kNumTimed = 3;
+TimerStat g_stats[kNumTimed];
 std::vector<PendingTiming> g_pending;
-const char *const kTimedKernels[2] = {"pi_build_f64", "lu_bordered"};
+const char *const kTimedKernels[kNumTimed] = {"pi_build_f64", "lu_bordered", "pi_build_mixed"};
 
 struct GwcError {
   int code;
@@ -214,6 +215,13 @@ struct Resident {
   int n_aux_pad, ldl;
   const int2 *tiles;
   int n_tiles;
+  // mixed-precision Pi build (precision != FP64)
+  int precision = GWC_PREC_FP64;
+  const float *Lf = nullptr;
+  const unsigned short *Bhi = nullptr, *Blo = nullptr;
+  const float *inv_colscale = nullptr, *acol = nullptr;
+  const int2 *mx_tiles = nullptr;
+  int mx_n_tiles = 0;
 };
 
 // Runs every task of `tl` (border width R) and writes W into W_out.
@@ -234,9 +242,10 @@ void run_screening(const Resident &rs, const TaskList &tl, int R, double2 *W_out
 
   if (n > gwc::lu_max_order())
     fail(GWC_ERR_UNSUPPORTED, "bordered order %d exceeds %d", n, gwc::lu_max_order());
-  DevBuf dG, dchr, dchi, dz, dn, dm, dob, dos, dbb, dst, dscr;
+  DevBuf dG, dchr, dchi, dz, dn, dm, dob, dos, dbb, dst, dscr, dts;
   dG.alloc(mat_bytes * F);
   dscr.alloc(gwc::lu_scratch_bytes(F));
+  dts.alloc((size_t)F * sizeof(float));
   dchr.alloc((size_t)F * rs.ldl * sizeof(double));
   dchi.alloc((size_t)F * rs.ldl * sizeof(double));
   dz.alloc(T * sizeof(double2));
@@ -258,13 +267,20 @@ void run_screening(const Resident &rs, const TaskList &tl, int R, double2 *W_out
     gwc::launch_chi(rs.eps, rs.n_occ, rs.n_virt, z, Fb, rs.ldl, dchr.as<double>(),
                     dchi.as<double>(), s);
     hipEvent_t ea = g_timing ? timing_mark(s) : nullptr;
-    gwc::launch_pi_build_f64(rs.Lp, rs.ldl, N, dchr.as<double>(), dchi.as<double>(), Fb,
-                             rs.tiles, rs.n_tiles, dG.as<double2>(), (long long)mat_elems, ldg, s);
+    if (rs.precision == GWC_PREC_FP64) {
+      gwc::launch_pi_build_f64(rs.Lp, rs.ldl, N, dchr.as<double>(), dchi.as<double>(), Fb,
+                               rs.tiles, rs.n_tiles, dG.as<double2>(), (long long)mat_elems, ldg, s);
+    } else {
+      gwc::launch_pi_build_mixed(rs.precision, rs.Lf, rs.Bhi, rs.Blo, rs.ldl, N, dchr.as<double>(),
+                                 dchi.as<double>(), rs.inv_colscale, rs.acol, dts.as<float>(), Fb,
+                                 rs.mx_tiles, rs.mx_n_tiles, dG.as<double2>(), (long long)mat_elems,
+                                 ldg, s);
+    }
     if (g_timing) {
       double fl = 0.0;
       for (int t = 0; t < Fb; ++t) fl += (tl.z[t0 + t].x == 0.0 ? 1.0 : 2.0);
       fl *= (double)N * (N + 1) * (double)rs.n_occ * rs.n_virt;
-      g_pending.push_back({0, ea, timing_mark(s), fl});
+      g_pending.push_back({rs.precision == GWC_PREC_FP64 ? 0 : 2, ea, timing_mark(s), fl});
     }
     gwc::launch_border(rs.M_oo, rs.M_ov, N, rs.n_occ, rs.n_virt, dn.as<int>() + t0,
                        dm.as<int>() + t0, Fb, R, dG.as<double2>(), (long long)mat_elems, ldg,
@@ -314,8 +330,8 @@ int sigma_core_impl(const gwc_system *sys, const gwc_sigma_args *args, gwc_sigma
     fail(GWC_ERR_INVALID_ARG, "unknown mode %d", args->mode);
   if (args->precision < GWC_PREC_FP64 || args->precision > GWC_PREC_FP8)
     fail(GWC_ERR_INVALID_ARG, "unknown precision %d", args->precision);
-  if (args->precision != GWC_PREC_FP64)
-    fail(GWC_ERR_UNSUPPORTED, "precision %d is not implemented in this build", args->precision);
+  if (args->precision == GWC_PREC_FP8)
+    fail(GWC_ERR_UNSUPPORTED, "precision %d (FP8) is not implemented in this build", args->precision);
   const bool full = args->mode == GWC_MODE_FULL;
   if (full && !out->sigma_c) fail(GWC_ERR_INVALID_ARG, "sigma_c is required in FULL mode");
 
@@ -389,7 +405,37 @@ int sigma_core_impl(const gwc_system *sys, const gwc_sigma_args *args, gwc_sigma
   HIPCHECK(hipGetLastError());
 
   Resident rs{dMoo, dMov, d_eps, N, no, nv, dL.as<double>(), n_aux_pad, ldl, d_tiles,
-                   (int)tiles.size()};
+              (int)tiles.size()};
+  DevBuf dLf, dBh, dBl, dcs, dics, dacol, dmxt;
+  if (args->precision != GWC_PREC_FP64) {
+    // split operands for the mixed-precision Pi build, rows padded to 256
+    const int rows_pad = (int)round_up(N, gwc::MX_TILE_COLS);
+    const size_t elems = (size_t)rows_pad * ldl;
+    dLf.alloc(elems * sizeof(float));
+    dBh.alloc(elems * sizeof(unsigned short));
+    dBl.alloc(elems * sizeof(unsigned short));
+    dcs.alloc(ldl * sizeof(float));
+    dics.alloc(ldl * sizeof(float));
+    dacol.alloc(ldl * sizeof(float));
+    gwc::launch_mixed_prep(args->precision, dL.as<double>(), n_aux_pad, rows_pad, ldl, dLf.as<float>(),
+                           dBh.as<unsigned short>(), dBl.as<unsigned short>(), dcs.as<float>(),
+                           dics.as<float>(), dacol.as<float>(), s);
+    std::vector<int2> mt;
+    const int nr_t = (N + gwc::MX_TILE_ROWS - 1) / gwc::MX_TILE_ROWS;
+    const int nc_t = (N + gwc::MX_TILE_COLS - 1) / gwc::MX_TILE_COLS;
+    for (int i = 0; i < nr_t; ++i)
+      for (int j = 0; j < nc_t; ++j)
+        if ((j + 1) * gwc::MX_TILE_COLS > i * gwc::MX_TILE_ROWS) mt.push_back(make_int2(i, j));
+    rs.precision = args->precision;
+    rs.Lf = dLf.as<float>();
+    rs.Bhi = dBh.as<unsigned short>();
+    rs.Blo = dBl.as<unsigned short>();
+    rs.inv_colscale = args->precision == GWC_PREC_FP16X3 ? dics.as<float>() : nullptr;
+    rs.acol = dacol.as<float>();
+    rs.mx_tiles = upload(dmxt, mt, s);
+    rs.mx_n_tiles = (int)mt.size();
+    HIPCHECK(hipGetLastError());
+  }
   std::vector<int> status;
 
   // ---- imaginary axis: W_imag[c][m][k]
@@ -554,8 +600,7 @@ int gwc_timing_enable(int on) {
     (void)hipEventDestroy(p.b);
   }
   g_pending.clear();
-  g_stats[0] = TimerStat{};
-  g_stats[1] = TimerStat{};
+  for (int k = 0; k < kNumTimed; ++k) g_stats[k] = TimerStat{};
   g_timing = on != 0;
   return GWC_OK;
 }
@@ -563,7 +608,7 @@ int gwc_timing_enable(int on) {
 int gwc_timing_get(const char *kernel, double *total_ms, long long *launches, double *flops) {
   std::lock_guard<std::mutex> lock(g_mutex);
   if (!kernel) return GWC_ERR_INVALID_ARG;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < kNumTimed; ++k) {
     if (std::string(kernel) == kTimedKernels[k]) {
       if (total_ms) *total_ms = g_stats[k].total_ms;
       if (launches) *launches = g_stats[k].launches;

@@ -35,6 +35,19 @@ void launch_chi(const double *eps, int n_occ, int n_virt, const double2 *z, int 
 void launch_pi_build_f64(const double *Lp, int ldl, int n_aux, const double *chi_re,
                          const double *chi_im, int F, const int2 *tiles, int n_tiles,
                          double2 *G, long long g_stride, int ldg, hipStream_t stream);
+// Mixed-precision Pi build (prec 1 = BF16X3, 2 = FP16X3).  Tiles are 64 x 256
+// blocks (MX_TILE_ROWS x MX_TILE_COLS); the split operands have their rows
+// padded to a multiple of MX_TILE_COLS.
+constexpr int MX_TILE_ROWS = 64;
+constexpr int MX_TILE_COLS = 256;
+void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, float *Lf,
+                       unsigned short *Bhi, unsigned short *Blo, float *colscale,
+                       float *inv_colscale, float *acol, hipStream_t stream);
+void launch_pi_build_mixed(int prec, const float *Lf, const unsigned short *Bhi,
+                           const unsigned short *Blo, int ldl, int n_aux, const double *chi_re,
+                           const double *chi_im, const float *inv_colscale, const float *acol,
+                           float *tscale, int F, const int2 *tiles, int n_tiles, double2 *G,
+                           long long g_stride, int ldg, hipStream_t stream);
 void launch_border(const double *M_oo, const double *M_ov, int n_aux, int n_occ, int n_virt,
                    const int *task_n, const int *task_m, int F, int R, double2 *G,
                    long long g_stride, int ldg, double *bb, hipStream_t stream);

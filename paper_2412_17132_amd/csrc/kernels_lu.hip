@@ -38,7 +38,10 @@ constexpr int PT = 512;                     // panel threads
 constexpr int PNW = PT / 64;
 constexpr int MAX_MOVES = 2 * NBO;
 constexpr int SW = 16;                      // trailing columns per swap/U12 workgroup
-constexpr int KCH = 16;                     // K chunk staged in LDS
+#ifndef GWC_LU_KCH
+#define GWC_LU_KCH 16
+#endif
+constexpr int KCH = GWC_LU_KCH;             // K chunk of the trailing update staged in LDS
 constexpr int NXCD = 8;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -79,8 +82,8 @@ struct PanelShared {
   double2 l16[16][16];
   union {
     struct {
-      double2 Ls[128][KCH + 1];
-      double2 Us[KCH][64 + 1];
+      double2 Ls[128][16 + 1];
+      double2 Us[16][64 + 1];
     } g;
     struct {
       double2 L11[NBO][NBO + 1];
@@ -116,21 +119,21 @@ __device__ void panel_gemm(double2 *__restrict__ A, int ldg, int r0, int r1, int
           cim[a][b][r] = v.y;
         }
       }
-    for (int kc = 0; kc < K; kc += KCH) {
-      const int kw = min(KCH, K - kc);
-      for (int idx = tid; idx < 128 * KCH; idx += PT) {
-        const int r = idx / KCH, t = idx - r * KCH;
+    for (int kc = 0; kc < K; kc += 16) {
+      const int kw = min(16, K - kc);
+      for (int idx = tid; idx < 128 * 16; idx += PT) {
+        const int r = idx / 16, t = idx - r * 16;
         sh.u.g.Ls[r][t] = (ra + r < r1 && t < kw) ? A[(long long)(ra + r) * ldg + kA + kc + t]
                                                   : make_double2(0.0, 0.0);
       }
-      for (int idx = tid; idx < KCH * 64; idx += PT) {
+      for (int idx = tid; idx < 16 * 64; idx += PT) {
         const int t = idx / 64, j = idx - t * 64;
         sh.u.g.Us[t][j] = (t < kw && ca + j < c1) ? A[(long long)(kA + kc + t) * ldg + ca + j]
                                                   : make_double2(0.0, 0.0);
       }
       __syncthreads();
 #pragma unroll
-      for (int kk = 0; kk < KCH; kk += 4) {
+      for (int kk = 0; kk < 16; kk += 4) {
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           const double2 lv = sh.u.g.Ls[wr + 16 * a + li][kk + lk];
@@ -245,49 +248,41 @@ lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, in
       }
       if (lane == 0) { sh.red_v[wave] = best; sh.red_i[wave] = bi; }
       __syncthreads();
-      if (tid == 0) {
-        double b = sh.red_v[0];
-        int p = sh.red_i[0];
-        for (int w = 1; w < PNW; ++w)
-          if (sh.red_v[w] > b || (sh.red_v[w] == b && sh.red_i[w] < p)) { b = sh.red_v[w]; p = sh.red_i[w]; }
-        sh.piv[rc - K0] = p;
+      // every thread reduces the wave maxima itself (same order, same result)
+      double bv = sh.red_v[0];
+      int p = sh.red_i[0];
+#pragma unroll
+      for (int w = 1; w < PNW; ++w)
+        if (sh.red_v[w] > bv || (sh.red_v[w] == bv && sh.red_i[w] < p)) { bv = sh.red_v[w]; p = sh.red_i[w]; }
+      if (tid == 0) sh.piv[rc - K0] = p;
+      // row rc lives in slot 0 of thread c, row p in slot sp of thread tp: the
+      // owner of p publishes the pivot row, the owner of rc its old content
+      const int tp = (p - k0) % PT, sp = (p - k0) / PT;
+      if (tid == tp) {
+#pragma unroll
+        for (int s = 0; s < RPT; ++s)
+          if (s == sp) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) sh.prow[j] = v[s][j];
+          }
+      }
+      if (p != rc && tid == c) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) sh.xbuf[0][j] = v[0][j];
       }
       __syncthreads();
-      const int p = sh.piv[rc - K0];
-      if (p != rc) {
-        // row rc lives in slot 0 of thread c, row p in slot sp of thread tp
-        const int tp = (p - k0) % PT, sp = (p - k0) / PT;
-        if (tid == tp) {
-#pragma unroll
-          for (int s = 0; s < RPT; ++s)
-            if (s == sp) {
-#pragma unroll
-              for (int j = 0; j < W; ++j) sh.xbuf[0][j] = v[s][j];
-            }
-        }
-        if (tid == c) {
-#pragma unroll
-          for (int j = 0; j < W; ++j) sh.xbuf[1][j] = v[0][j];
-        }
-        __syncthreads();
-        if (tid == c) {
-#pragma unroll
-          for (int j = 0; j < W; ++j) v[0][j] = sh.xbuf[0][j];
-        }
-        if (tid == tp) {
-#pragma unroll
-          for (int s = 0; s < RPT; ++s)
-            if (s == sp) {
-#pragma unroll
-              for (int j = 0; j < W; ++j) v[s][j] = sh.xbuf[1][j];
-            }
-        }
-      }
       if (tid == c) {
 #pragma unroll
-        for (int j = 0; j < W; ++j) sh.prow[j] = v[0][j];
+        for (int j = 0; j < W; ++j) v[0][j] = sh.prow[j];
       }
-      __syncthreads();
+      if (p != rc && tid == tp) {
+#pragma unroll
+        for (int s = 0; s < RPT; ++s)
+          if (s == sp) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) v[s][j] = sh.xbuf[0][j];
+          }
+      }
       const double2 d = sh.prow[c];
       double2 inv;
       if (d.x == 0.0 && d.y == 0.0) {
