@@ -143,6 +143,98 @@ def _satellites(w, A, e_qp, Z, eta, min_sep_ev=0.5, rel_height=0.05):
     return out
 
 
+def serve_main(args):
+    """Poisson arrivals of single-core-state requests (DECOUPLED + A(w)) from a
+    pool of device-resident molecules with N_basis ~ U{40..max}, N_aux = 4 N_basis,
+    N_occ = N_basis / 15; prints one JSON line with p50/p99 latency and solves/s."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2412_17132_amd.serve import ResidentSystem, Server
+    from workloads import EV_PER_HA, serving_request_config, system_from_config
+
+    if args.gpus != 1:
+        print("bench.py --serve runs on one GPU only", file=sys.stderr)
+        sys.exit(2)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+    rng = np.random.default_rng(5)
+    sizes = sorted(int(x) for x in rng.integers(40, args.serve_max_nbasis + 1, args.serve_pool))
+    mols = [system_from_config(serving_request_config(nb, 1000 + i)) for i, nb in enumerate(sizes)]
+    res = [ResidentSystem.from_system(s) for s in mols]
+    nbasis = [s.n_basis for s in mols]
+    for s in mols:  # host copies are no longer needed
+        s.M_oo = s.M_ov = None
+    precision = args.precision
+    srv = Server(n_slots=args.serve_slots, hbm_budget_bytes=args.serve_budget_gb * 2 ** 30)
+
+    def submit(i, c):
+        s = mols[i]
+        return srv.submit(res[i], c, s.omega_imag, s.w_imag, s.omega_real[c], s.eta, mode="decoupled",
+                          precision=precision, n_t=2 ** 18, d_omega=0.01 / EV_PER_HA, n_out=3500,
+                          omega_out_min_rel=-30 / EV_PER_HA)
+
+    # warm-up: one request per molecule (also builds the split operands)
+    for i, s in enumerate(mols):
+        srv.wait(submit(i, 0))
+    gaps = rng.exponential(1.0 / args.serve_rate, args.serve_requests)
+    picks = [(int(rng.integers(len(mols))), None) for _ in range(args.serve_requests)]
+    picks = [(i, int(rng.integers(len(mols[i].core_idx)))) for i, _ in picks]
+    tickets = [None] * args.serve_requests
+
+    def feeder():
+        t0 = time.perf_counter()
+        at = 0.0
+        for k, (i, c) in enumerate(picks):
+            at += gaps[k]
+            delay = at - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[k] = submit(i, c)
+
+    th = threading.Thread(target=feeder)
+    t_start = time.perf_counter()
+    th.start()
+    th.join()
+    out = [srv.wait(t) for t in tickets]
+    wall = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    lat = np.array([r["t_end"] - r["t_submit"] for r in out])
+    first = min(r["t_submit"] for r in out)
+    last = max(r["t_end"] for r in out)
+    nbs = [nbasis[i] for i, _ in picks]
+    line = {
+        "metric": METRIC,
+        "value": len(out) / (last - first),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(out),
+        "warmup": len(mols),
+        "ms_per_step": 1e3 * (last - first) / len(out),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == "fp64" else precision,
+        "data": "synthetic",
+        "config": {"workload": f"serving: Poisson stream, lambda={args.serve_rate}/s, {len(out)} "
+                               f"single-core-state requests (DECOUPLED + A(w)), {len(mols)} resident "
+                               f"molecules N_basis {sizes}, N_aux = 4 N_basis",
+                   "precision": precision, "slots": args.serve_slots,
+                   "hbm_budget_gb": args.serve_budget_gb, "parallelism": "single-gpu"},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "mean": float(lat.mean()), "per": "request (arrival to result)"},
+        "serving": {"offered_rate": args.serve_rate,
+                    "achieved_rate": len(out) / (last - first),
+                    "wall_s": wall, "peak_concurrent_requests": st["peak_active"],
+                    "peak_in_use_gb": st["peak_in_use_bytes"] / 2 ** 30,
+                    "mean_nbasis": float(np.mean(nbs))},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +251,15 @@ def main():
                          "E_QP / satellite-position errors against the FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tasks", type=int, default=24)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark instead: a Poisson stream of single-core-state "
+                         "requests through the continuous-batching server")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="arrivals per second")
+    ap.add_argument("--serve-pool", type=int, default=6, help="distinct molecules (device-resident)")
+    ap.add_argument("--serve-max-nbasis", type=int, default=1100)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=96.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -174,6 +275,8 @@ def main():
                           "launches": 3}))
         return
 
+    if args.serve:
+        return serve_main(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout "
               "is a design note, not an implemented path.", file=sys.stderr)

@@ -167,6 +167,74 @@ typedef struct {
 int gwc_spectral_cumulant(const gwc_cumulant_args *args, double *A_out, double *z_out,
                           void *hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Device-resident systems (serving form).  gwc_system_create validates a
+ * system as gwc_sigma_core does and keeps library-owned device copies of eps,
+ * M_oo, M_ov and the packed L (plus, on first use, the split operands of the
+ * mixed-precision Pi build) until gwc_system_destroy; the caller's arrays may
+ * be freed after create returns.  gwc_sigma_core_resident is gwc_sigma_core on
+ * such a handle (same arguments, outputs and errors).  A handle may be used by
+ * several threads and server requests at once; destroy waits for the device
+ * and must not race with calls that use the handle. */
+typedef struct gwc_resident_system_s *gwc_system_handle;
+int gwc_system_create(const gwc_system *sys, gwc_system_handle *handle);
+int gwc_system_destroy(gwc_system_handle handle);
+int gwc_sigma_core_resident(gwc_system_handle handle, const gwc_sigma_args *args,
+                            gwc_sigma_out *out, void *hip_stream);
+
+/* Request server (continuous batching of single-core-state solves).
+ * n_slots worker threads, each with its own HIP stream, take queued requests
+ * in arrival order as soon as a slot is free and the request's predicted
+ * device footprint fits in hbm_budget_bytes beside the running requests;
+ * requests that can never fit are refused at submit (GWC_ERR_OUT_OF_MEMORY).
+ * batch_bytes (0 = budget / 4) bounds the batched matrices of one launch of a
+ * request and is the same for every request, so each result is independent
+ * of what runs beside it.  One request = gwc_sigma_core for one core state
+ * (mode, precision as given) followed by gwc_spectral_cumulant of its
+ * Im Sigma^dec when n_t > 0, with the output window starting at
+ * E_QP + omega_out_min_rel.  Times are seconds since server creation. */
+typedef struct gwc_server_s *gwc_server_handle;
+typedef struct {
+  int32_t n_slots;          /* 1..64 */
+  double hbm_budget_bytes;  /* > 0 */
+  double batch_bytes;       /* 0 = hbm_budget_bytes / 4 */
+} gwc_server_config;
+typedef struct {
+  gwc_system_handle system;
+  int32_t core_idx;                   /* < n_occ of the system */
+  int32_t n_imag;
+  const double *omega_imag, *w_imag;  /* host arrays, copied at submit */
+  int32_t n_real;
+  const double *omega_real;           /* host array, copied at submit */
+  double eta, vxc;
+  int32_t mode, precision;
+  int32_t n_t;                        /* 0 = no cumulant */
+  double d_omega;
+  int32_t n_out;
+  double omega_out_min_rel;
+} gwc_request;
+typedef struct {
+  int32_t status;                     /* gwc_status of the request */
+  double e_qp, sigma_x, sigma_c_eps[2], z[2];
+  double *im_sigma_dec;               /* [n_real] host buffer to fill, or NULL */
+  double *A;                          /* [n_out] host buffer to fill, or NULL */
+  double *sigma_c;                    /* [n_real][2] host buffer (FULL mode), or NULL */
+  double t_submit, t_start, t_end;
+  double footprint_bytes;
+} gwc_request_result;
+typedef struct {
+  int32_t queued, active, peak_active;
+  long long completed;
+  double in_use_bytes, peak_in_use_bytes, budget_bytes;
+} gwc_server_stats_t;
+int gwc_server_create(const gwc_server_config *cfg, gwc_server_handle *server);
+int gwc_server_submit(gwc_server_handle server, const gwc_request *request, int64_t *ticket);
+/* Blocks until the request has finished; fills `result` and returns its status. */
+int gwc_server_wait(gwc_server_handle server, int64_t ticket, gwc_request_result *result);
+int gwc_server_stats(gwc_server_handle server, gwc_server_stats_t *stats);
+/* Finishes every queued request, then stops the workers. */
+int gwc_server_destroy(gwc_server_handle server);
+
 /* Kernel timing (diagnostics for profiling harnesses, not part of the method).
  * gwc_timing_enable(1) clears the counters and, until gwc_timing_enable(0),
  * brackets every launch of the named hot kernels with HIP events recorded on

@@ -35,6 +35,14 @@ EXPORTED_SYMBOLS = (
     "gwc_version",
     "gwc_timing_enable",
     "gwc_timing_get",
+    "gwc_system_create",
+    "gwc_system_destroy",
+    "gwc_sigma_core_resident",
+    "gwc_server_create",
+    "gwc_server_submit",
+    "gwc_server_wait",
+    "gwc_server_stats",
+    "gwc_server_destroy",
 )
 
 
@@ -68,6 +76,39 @@ class GwcCumulantArgs(Structure):
         ("eps_n", c_double), ("e_qp", c_double), ("eta", c_double),
         ("n_t", c_int32), ("d_omega", c_double),
         ("n_out", c_int32), ("omega_out_min", c_double),
+    ]
+
+
+class GwcServerConfig(Structure):
+    _fields_ = [("n_slots", c_int32), ("hbm_budget_bytes", c_double), ("batch_bytes", c_double)]
+
+
+class GwcRequest(Structure):
+    _fields_ = [
+        ("system", c_void_p), ("core_idx", c_int32),
+        ("n_imag", c_int32), ("omega_imag", c_void_p), ("w_imag", c_void_p),
+        ("n_real", c_int32), ("omega_real", c_void_p),
+        ("eta", c_double), ("vxc", c_double), ("mode", c_int32), ("precision", c_int32),
+        ("n_t", c_int32), ("d_omega", c_double), ("n_out", c_int32),
+        ("omega_out_min_rel", c_double),
+    ]
+
+
+class GwcRequestResult(Structure):
+    _fields_ = [
+        ("status", c_int32), ("e_qp", c_double), ("sigma_x", c_double),
+        ("sigma_c_eps", c_double * 2), ("z", c_double * 2),
+        ("im_sigma_dec", c_void_p), ("A", c_void_p), ("sigma_c", c_void_p),
+        ("t_submit", c_double), ("t_start", c_double), ("t_end", c_double),
+        ("footprint_bytes", c_double),
+    ]
+
+
+class GwcServerStats(Structure):
+    _fields_ = [
+        ("queued", c_int32), ("active", c_int32), ("peak_active", c_int32),
+        ("completed", ctypes.c_longlong), ("in_use_bytes", c_double),
+        ("peak_in_use_bytes", c_double), ("budget_bytes", c_double),
     ]
 
 
@@ -106,6 +147,23 @@ def load(path: str = LIB_PATH):
     lib.gwc_timing_get.argtypes = [ctypes.c_char_p, POINTER(c_double), POINTER(ctypes.c_longlong),
                                    POINTER(c_double)]
     lib.gwc_timing_get.restype = c_int
+    lib.gwc_system_create.argtypes = [POINTER(GwcSystem), POINTER(c_void_p)]
+    lib.gwc_system_create.restype = c_int
+    lib.gwc_system_destroy.argtypes = [c_void_p]
+    lib.gwc_system_destroy.restype = c_int
+    lib.gwc_sigma_core_resident.argtypes = [c_void_p, POINTER(GwcSigmaArgs), POINTER(GwcSigmaOut),
+                                            c_void_p]
+    lib.gwc_sigma_core_resident.restype = c_int
+    lib.gwc_server_create.argtypes = [POINTER(GwcServerConfig), POINTER(c_void_p)]
+    lib.gwc_server_create.restype = c_int
+    lib.gwc_server_submit.argtypes = [c_void_p, POINTER(GwcRequest), POINTER(ctypes.c_int64)]
+    lib.gwc_server_submit.restype = c_int
+    lib.gwc_server_wait.argtypes = [c_void_p, ctypes.c_int64, POINTER(GwcRequestResult)]
+    lib.gwc_server_wait.restype = c_int
+    lib.gwc_server_stats.argtypes = [c_void_p, POINTER(GwcServerStats)]
+    lib.gwc_server_stats.restype = c_int
+    lib.gwc_server_destroy.argtypes = [c_void_p]
+    lib.gwc_server_destroy.restype = c_int
     _lib = lib
     return lib
 

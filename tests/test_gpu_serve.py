@@ -1,0 +1,115 @@
+"""Serving form: device-resident systems and the continuous-batching server.
+
+* a resident system gives the same results as the one-shot entry point;
+* each request's result is the same alone and in a mix of concurrent requests
+  from molecules of different sizes (bitwise: the work of a request is
+  decomposed the same way whatever runs beside it);
+* admission by HBM footprint: oversize requests are refused, and a budget that
+  holds one request at a time serialises them.
+"""
+import numpy as np
+import pytest
+
+import paper_2412_17132_amd as gwc
+from paper_2412_17132_amd.serve import ResidentSystem, Server
+from workloads import EV_PER_HA, serving_request_config, system_from_config
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _molecules():
+    out = []
+    for nb, seed in ((40, 1001), (75, 1002), (130, 1003)):
+        cfg = serving_request_config(nb, seed)
+        out.append(system_from_config(cfg))
+    return out
+
+
+def _submit(srv, rs, s, core, precision="fp64", mode="decoupled"):
+    return srv.submit(rs, core, s.omega_imag, s.w_imag, s.omega_real[core], s.eta, mode=mode,
+                      precision=precision, n_t=2 ** 14, d_omega=0.01 / EV_PER_HA, n_out=2000,
+                      omega_out_min_rel=-15 / EV_PER_HA)
+
+
+def test_resident_matches_one_shot():
+    s = _molecules()[1]
+    rs = ResidentSystem.from_system(s)
+    a = rs.sigma_core(s.core_idx, s.omega_imag, s.w_imag, s.omega_real, s.eta, mode="full")
+    b = gwc.gwc_sigma_core(s.eps, s.occ, s.M_oo, s.M_ov, s.core_idx, s.omega_imag, s.w_imag,
+                           s.omega_real, s.eta, mode="full")
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    rs.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_alone_equals_mix(precision):
+    mols = _molecules()
+    res = [ResidentSystem.from_system(s) for s in mols]
+    jobs = [(i, c) for i, s in enumerate(mols) for c in range(s.n_core)]
+    # alone: one slot, one request at a time
+    srv = Server(n_slots=1, hbm_budget_bytes=8 << 30)
+    alone = {}
+    for i, c in jobs:
+        t = _submit(srv, res[i], mols[i], c, precision)
+        alone[(i, c)] = srv.wait(t)
+    srv.close()
+    # mix: four slots, everything submitted at once (twice over)
+    srv = Server(n_slots=4, hbm_budget_bytes=8 << 30)
+    tickets = [((i, c), _submit(srv, res[i], mols[i], c, precision)) for _ in range(2) for i, c in jobs]
+    mixed = [(key, srv.wait(t)) for key, t in tickets]
+    st = srv.stats()
+    srv.close()
+    print(f"{precision}: peak concurrent requests {st['peak_active']}, completed {st['completed']}")
+    assert st["peak_active"] > 1
+    for key, r in mixed:
+        a = alone[key]
+        assert r["e_qp"] == a["e_qp"] and r["sigma_x"] == a["sigma_x"], key
+        assert np.array_equal(r["im_sigma_dec"], a["im_sigma_dec"]), key
+        assert np.array_equal(r["A"], a["A"]), key
+        assert r["z"] == a["z"], key
+    for r in res:
+        r.close()
+
+
+def test_server_results_match_direct_call():
+    s = _molecules()[2]
+    rs = ResidentSystem.from_system(s)
+    srv = Server(n_slots=2, hbm_budget_bytes=8 << 30)
+    t = [_submit(srv, rs, s, c) for c in range(s.n_core)]
+    out = [srv.wait(x) for x in t]
+    srv.close()
+    ref = rs.sigma_core(s.core_idx, s.omega_imag, s.w_imag, s.omega_real, s.eta, mode="decoupled")
+    for c in range(s.n_core):
+        assert abs(out[c]["e_qp"] - ref["e_qp"][c]) <= 1e-12 * abs(ref["e_qp"][c])
+        assert np.allclose(out[c]["im_sigma_dec"], ref["im_sigma_dec"][c], rtol=1e-12, atol=1e-15)
+    rs.close()
+
+
+def test_admission_by_footprint():
+    mols = _molecules()
+    res = [ResidentSystem.from_system(s) for s in mols]
+    # find the footprint of the largest request, then size the budget to hold one
+    probe = Server(n_slots=1, hbm_budget_bytes=8 << 30, batch_bytes=64 << 20)
+    t = _submit(probe, res[2], mols[2], 0)
+    fp = probe.wait(t)["footprint_bytes"]
+    probe.close()
+    srv = Server(n_slots=4, hbm_budget_bytes=1.5 * fp, batch_bytes=64 << 20)
+    tickets = [_submit(srv, res[2], mols[2], c) for c in range(mols[2].n_core)] * 1
+    tickets += [_submit(srv, res[2], mols[2], 0)]
+    out = [srv.wait(x) for x in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["peak_active"] == 1
+    assert st["peak_in_use_bytes"] <= st["budget_bytes"]
+    starts = sorted((r["t_start"], r["t_end"]) for r in out)
+    for (s0, e0), (s1, e1) in zip(starts, starts[1:]):
+        assert s1 >= e0  # one at a time
+    tiny = Server(n_slots=2, hbm_budget_bytes=fp / 2, batch_bytes=64 << 20)
+    with pytest.raises(gwc.GwcError) as ei:
+        _submit(tiny, res[2], mols[2], 0)
+    assert ei.value.status == -6
+    tiny.close()
+    for r in res:
+        r.close()
