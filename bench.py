@@ -120,6 +120,114 @@ def cpu_baseline(system, mode, n_tasks_per_core, budget_tasks=24):
     }
 
 
+def measure_peaks(gwc):
+    """Device peaks re-measured by the library's probes (register-operand MFMA
+    loops, a 4 GiB device copy), beside the datasheet figures."""
+    return {
+        "fp64_mfma_tflops": gwc.probe_peak("fp64_mfma"),
+        "bf16_mfma_tflops": gwc.probe_peak("bf16_mfma"),
+        "fp16_mfma_tflops": gwc.probe_peak("fp16_mfma"),
+        "hbm_copy_gbs": gwc.probe_peak("hbm_copy"),
+        "datasheet": {"fp64_mfma_tflops": 78.6, "bf16_mfma_tflops": 2500.0,
+                      "fp16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0},
+    }
+
+
+def sampled_main(args):
+    """Large workloads (c3, c4) whose FULL solve takes minutes to hours: time
+    one core state at two real-grid sizes (1 and --sample-points points, spread
+    over its grid) on a device-resident system, take the per-task cost from the
+    difference, and extrapolate to the full grid.  Labelled as sampled."""
+    import numpy as np
+    import torch
+
+    import paper_2412_17132_amd as gwc
+    from oracle import sigma as OS  # task count only (host bookkeeping)
+    from paper_2412_17132_amd.serve import ResidentSystem
+    from workloads import CONFIGS, EV_PER_HA, system_from_config
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = CONFIGS[args.config]
+    s = system_from_config(cfg)
+    n_core = s.n_core
+    n_tasks_full = OS.count_residue_tasks(s.eps, s.occ, s.core_idx, s.omega_real, args.mode)
+    rs = ResidentSystem.from_system(s)
+    core = s.core_idx[:1]
+    n_real = s.omega_real.shape[1]
+
+    def run(k):
+        idx = np.unique(np.linspace(0, n_real - 1, k).round().astype(int))
+        w = np.ascontiguousarray(s.omega_real[:1, idx])
+        tasks = OS.count_residue_tasks(s.eps, s.occ, core, w, args.mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = rs.sigma_core(core, s.omega_imag, s.w_imag, w, s.eta, mode=args.mode,
+                            precision=args.precision)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, tasks, out
+
+    print(f"sampled {cfg.name}: warm-up", file=sys.stderr, flush=True)
+    run(1)
+    gwc.timing_enable(True)
+    t_a, n_a, _ = run(1)
+    print(f"sampled {cfg.name}: 1 point, {n_a} tasks, {t_a:.2f} s", file=sys.stderr, flush=True)
+    t_b, n_b, out = run(args.sample_points)
+    print(f"sampled {cfg.name}: {args.sample_points} points, {n_b} tasks, {t_b:.2f} s",
+          file=sys.stderr, flush=True)
+    pi = gwc.timing_get("pi_build_f64" if args.precision == "fp64" else "pi_build_mixed")
+    lu = gwc.timing_get("lu_bordered")
+    gwc.timing_enable(False)
+    t_task = (t_b - t_a) / (n_b - n_a)
+    t_fixed = max(t_a - n_a * t_task, 0.0)
+    d_omega = 0.01 / EV_PER_HA
+    e_qp = float(out["e_qp"][0])
+    wg = torch.as_tensor(np.ascontiguousarray(s.omega_real[0]), device="cuda:0")
+    im_full = torch.zeros_like(wg)  # cumulant cost does not depend on the values
+    gwc.gwc_spectral_cumulant(wg, im_full, float(s.eps[core[0]]), e_qp, s.eta, 2 ** 18, d_omega,
+                              3500, e_qp - 30 / EV_PER_HA)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gwc.gwc_spectral_cumulant(wg, im_full, float(s.eps[core[0]]), e_qp, s.eta, 2 ** 18, d_omega,
+                              3500, e_qp - 30 / EV_PER_HA)
+    torch.cuda.synchronize()
+    t_cum = time.perf_counter() - t0
+    t_solve = t_fixed + (n_tasks_full / n_core) * t_task + t_cum
+    pi_tf = pi["flops"] / (pi["total_ms"] / 1e3) / 1e12 if pi["total_ms"] > 0 else 0.0
+    lu_tf = lu["flops"] / (lu["total_ms"] / 1e3) / 1e12 if lu["total_ms"] > 0 else 0.0
+    peak = FP64_MFMA_PEAK_TFLOPS if args.precision == "fp64" else 2500.0
+    mfma = pi_tf if args.precision == "fp64" else 3.0 * pi_tf
+    rs.close()
+    line = {
+        "metric": METRIC,
+        "value": 1.0 / t_solve,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 2,
+        "warmup": 1,
+        "ms_per_step": t_solve * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.description} -- SAMPLED: one core state at 1 and "
+                               f"{args.sample_points} real points ({n_a} and {n_b} residue tasks), "
+                               f"extrapolated to {n_tasks_full / n_core:.0f} tasks per core state",
+                   "n_basis": cfg.n_basis, "n_occ": cfg.n_occ, "n_core": n_core, "n_aux": cfg.n_aux,
+                   "n_imag": cfg.n_imag, "n_real": n_real, "mode": args.mode,
+                   "precision": args.precision, "parallelism": "single-gpu"},
+        "sampled": {"t_fixed_s": t_fixed, "t_task_ms": t_task * 1e3, "t_cumulant_s": t_cum,
+                    "tasks_per_core_state": n_tasks_full / n_core},
+        "roofline": {"bound": "mfma", "achieved": mfma, "peak": peak, "unit": "TFLOP/s",
+                     "frac": mfma / peak, "traffic": None,
+                     "kernel": "pi_build_f64" if args.precision == "fp64" else "pi_build_mixed",
+                     "avg_launch_ms": pi["total_ms"] / max(pi["launches"], 1)},
+        "kernels": {"pi_build": {"ms": pi["total_ms"], "launches": pi["launches"], "tflops": pi_tf},
+                    "lu_bordered": {"ms": lu["total_ms"], "launches": lu["launches"], "tflops": lu_tf}},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def _satellites(w, A, e_qp, Z, eta, min_sep_ev=0.5, rel_height=0.05):
     """Satellite peaks: local maxima of A - Z L_eta(w - E_QP) more than 0.5 eV
     below E_QP with height >= 5 % of that remainder's maximum there, refined by
@@ -198,7 +306,11 @@ def serve_main(args):
     t_start = time.perf_counter()
     th.start()
     th.join()
-    out = [srv.wait(t) for t in tickets]
+    out = []
+    for k, t in enumerate(tickets):
+        out.append(srv.wait(t))
+        if (k + 1) % 20 == 0:
+            print(f"serve: {k + 1}/{len(tickets)} requests done", file=sys.stderr, flush=True)
     wall = time.perf_counter() - t_start
     st = srv.stats()
     srv.close()
@@ -250,6 +362,12 @@ def main():
                     help="also time this mixed-precision form and report its speed-up and its "
                          "E_QP / satellite-position errors against the FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the peak-rate probes")
+    ap.add_argument("--no-decoupled", action="store_true",
+                    help="skip the DECOUPLED-mode leg reported beside the FULL value")
+    ap.add_argument("--sample-points", type=int, default=0,
+                    help="sampled run for large workloads (c3, c4): one core state at 1 and this "
+                         "many real points, extrapolated to the full grid")
     ap.add_argument("--cpu-tasks", type=int, default=24)
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark instead: a Poisson stream of single-core-state "
@@ -275,12 +393,14 @@ def main():
                           "launches": 3}))
         return
 
-    if args.serve:
-        return serve_main(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout "
               "is a design note, not an implemented path.", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        return serve_main(args)
+    if args.sample_points:
+        return sampled_main(args)
 
     import numpy as np
     import torch
@@ -426,6 +546,29 @@ def main():
             "satellite_max_shift_mev": worst * EV_PER_HA * 1e3,
             "sigma_c_rel_err": sc_err,
         }
+    if args.mode == "full" and not args.no_decoupled:
+        mode_full = args.mode
+        args.mode = "decoupled"
+        step()  # warm-up
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        el_d = time.perf_counter() - td
+        args.mode = mode_full
+        res["decoupled"] = {
+            "value": solves / el_d, "unit": "solves/s", "ms_per_step": el_d / args.steps * 1e3,
+            "residue_tasks_per_step": OS.count_residue_tasks(s.eps, s.occ, s.core_idx, s.omega_real,
+                                                             "decoupled"),
+            "precision": args.precision,
+        }
+    if not args.no_peaks:
+        pk = measure_peaks(gwc)
+        res["peaks_measured"] = pk
+        if args.precision == "fp64":
+            res["roofline"]["peak_measured"] = pk["fp64_mfma_tflops"]
+            res["roofline"]["frac_of_measured"] = achieved / pk["fp64_mfma_tflops"]
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(s, args.mode, n_tasks / n_core, args.cpu_tasks)
     print(json.dumps(res), flush=True)

@@ -247,6 +247,21 @@ int gwc_server_destroy(gwc_server_handle server);
 int gwc_timing_enable(int on);
 int gwc_timing_get(const char *kernel, double *total_ms, long long *launches, double *flops);
 
+/* Peak-rate probe (diagnostics, not part of the method): runs a
+ * microbenchmark on the current device, ordered on hip_stream (NULL: default
+ * stream), and returns through *value what the device reaches:
+ *   kind 0  FP64 MFMA (v_mfma_f64_16x16x4f64), TFLOP/s
+ *   kind 1  BF16 MFMA (v_mfma_f32_16x16x32_bf16), TFLOP/s
+ *   kind 2  FP16 MFMA (v_mfma_f32_16x16x32_f16), TFLOP/s
+ *   kind 3  device-memory copy of 4 GiB, GB/s counting bytes read + written
+ * The MFMA probes keep operands in registers (independent accumulator chains,
+ * no memory traffic in the loop); each figure is the median of five timed
+ * launches after one untimed launch.  Allocates temporaries (2 x 4 GiB for
+ * kind 3) from the stream-ordered pool and frees them before returning.
+ * GWC_ERR_INVALID_ARG for another kind or a NULL value; GWC_ERR_DEVICE or
+ * GWC_ERR_OUT_OF_MEMORY on a HIP failure. */
+int gwc_probe_peak(int kind, double *value, void *hip_stream);
+
 /* Message describing the last non-OK return on the calling thread ("" if none). */
 const char *gwc_last_error(void);
 

@@ -43,6 +43,7 @@ EXPORTED_SYMBOLS = (
     "gwc_server_wait",
     "gwc_server_stats",
     "gwc_server_destroy",
+    "gwc_probe_peak",
 )
 
 
@@ -164,6 +165,8 @@ def load(path: str = LIB_PATH):
     lib.gwc_server_stats.restype = c_int
     lib.gwc_server_destroy.argtypes = [c_void_p]
     lib.gwc_server_destroy.restype = c_int
+    lib.gwc_probe_peak.argtypes = [c_int, POINTER(c_double), c_void_p]
+    lib.gwc_probe_peak.restype = c_int
     _lib = lib
     return lib
 

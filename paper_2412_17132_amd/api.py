@@ -148,5 +148,16 @@ def timing_get(kernel: str) -> dict:
     return {"total_ms": ms.value, "launches": n.value, "flops": fl.value}
 
 
+PROBE_KINDS = {"fp64_mfma": 0, "bf16_mfma": 1, "fp16_mfma": 2, "hbm_copy": 3}
+
+
+def probe_peak(kind: str) -> float:
+    """Measured device peak: MFMA TFLOP/s for the *_mfma kinds, GB/s for hbm_copy."""
+    import ctypes
+    v = ctypes.c_double()
+    N.check(N.load().gwc_probe_peak(PROBE_KINDS[kind], ctypes.byref(v), None))
+    return v.value
+
+
 def version() -> int:
     return int(N.load().gwc_version())

@@ -84,4 +84,8 @@ void launch_fft_inverse(double2 *buf_a, double2 *buf_b, int log2n, double2 **res
                         hipStream_t stream);
 void launch_extract_spectrum(const double2 *Gw, int n_out, double *A_out, hipStream_t stream);
 
+// Peak-rate probes (diagnostics): kind 0 FP64 MFMA, 1 BF16 MFMA, 2 FP16 MFMA
+// (TFLOP/s), 3 HBM copy (GB/s, read + write).
+hipError_t probe_peak(int kind, hipStream_t s, double *value);
+
 }  // namespace gwc
