@@ -71,20 +71,25 @@ __device__ __forceinline__ bool xcd_map(int wg, int items, int F, int &f, int &i
 
 // ===========================================================================
 // P: panel factorisation
+constexpr int WMAX = 16;  // widest register column block of the panel
+
 struct PanelShared {
   double red_v[PNW];
   int red_i[PNW];
   int piv[NBO];
   int mrow[MAX_MOVES], mcont[MAX_MOVES];
   int flags;
-  double2 prow[16];
-  double2 xbuf[2][16];
-  double2 l16[16][16];
+  int bcnt;
+  int brow[2 * WMAX], bcont[2 * WMAX];  // one block's interchanges as net row moves
+  int bdst[2 * WMAX], bsrc[2 * WMAX];
+  double2 prow[WMAX];
+  double2 xbuf[WMAX];
+  double2 lbb[WMAX][WMAX + 1];
   union {
     struct {
-      double2 Ls[128][16 + 1];
-      double2 Us[16][64 + 1];
-    } g;
+      double2 stage[2 * WMAX][NBO];  // moved rows of the panel columns outside the block
+      double2 U[WMAX][NBO];          // U rows of the block on the columns to its right
+    } blk;
     struct {
       double2 L11[NBO][NBO + 1];
       double2 X[NBO][NBO + 1];
@@ -92,121 +97,23 @@ struct PanelShared {
   } u;
 };
 
-// A[r0:r1, c0:c1] -= A[r0:r1, kA:kA+K] A[kA:kA+K, c0:c1] (inside the panel;
-// 8 waves as 4 x 2 quadrants of a 128 x 64 tile).
-__device__ void panel_gemm(double2 *__restrict__ A, int ldg, int r0, int r1, int c0, int c1,
-                           int kA, int K, PanelShared &sh) {
-  if (r1 <= r0 || c1 <= c0 || K <= 0) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int mt = (r1 - r0 + 127) / 128, nt = (c1 - c0 + 63) / 64;
-  for (int tile = 0; tile < mt * nt; ++tile) {
-    const int ti = tile / nt, tj = tile - ti * nt;
-    const int ra = r0 + ti * 128, ca = c0 + tj * 64;
-    d4 cre[2][2], cim[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int col = ca + wc + 16 * b + li;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = ra + wr + 16 * a + 4 * r + lk;
-          double2 v = make_double2(0.0, 0.0);
-          if (row < r1 && col < c1) v = A[(long long)row * ldg + col];
-          cre[a][b][r] = v.x;
-          cim[a][b][r] = v.y;
-        }
-      }
-    for (int kc = 0; kc < K; kc += 16) {
-      const int kw = min(16, K - kc);
-      for (int idx = tid; idx < 128 * 16; idx += PT) {
-        const int r = idx / 16, t = idx - r * 16;
-        sh.u.g.Ls[r][t] = (ra + r < r1 && t < kw) ? A[(long long)(ra + r) * ldg + kA + kc + t]
-                                                  : make_double2(0.0, 0.0);
-      }
-      for (int idx = tid; idx < 16 * 64; idx += PT) {
-        const int t = idx / 64, j = idx - t * 64;
-        sh.u.g.Us[t][j] = (t < kw && ca + j < c1) ? A[(long long)(kA + kc + t) * ldg + ca + j]
-                                                  : make_double2(0.0, 0.0);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const double2 lv = sh.u.g.Ls[wr + 16 * a + li][kk + lk];
-          const double ar = -lv.x, ai = -lv.y;
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            const double2 uv = sh.u.g.Us[kk + lk][wc + 16 * b + li];
-            cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.x, cre[a][b], 0, 0, 0);
-            cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, uv.y, cre[a][b], 0, 0, 0);
-            cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.y, cim[a][b], 0, 0, 0);
-            cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, uv.x, cim[a][b], 0, 0, 0);
-          }
-        }
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int col = ca + wc + 16 * b + li;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = ra + wr + 16 * a + 4 * r + lk;
-          if (row < r1 && col < c1)
-            A[(long long)row * ldg + col] = make_double2(cre[a][b][r], cim[a][b][r]);
-        }
-      }
-  }
-}
-
-// Rows [k0, k0+kb) of columns [c0, c1): unit-lower solve with the kb x kb
-// diagonal block.
-__device__ void panel_trsm(double2 *__restrict__ A, int ldg, int k0, int kb, int c0, int c1,
-                           PanelShared &sh) {
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < 16 * 16; idx += PT) {
-    const int i = idx / 16, t = idx - i * 16;
-    sh.l16[i][t] = (i < kb && t < kb) ? A[(long long)(k0 + i) * ldg + k0 + t] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int j = c0 + tid; j < c1; j += PT) {
-    for (int i = 1; i < kb; ++i) {
-      double2 acc = A[(long long)(k0 + i) * ldg + j];
-      for (int t = 0; t < i; ++t) acc = csub(acc, cmul(sh.l16[i][t], A[(long long)(k0 + t) * ldg + j]));
-      A[(long long)(k0 + i) * ldg + j] = acc;
-    }
-  }
-  __syncthreads();
-}
-
-// Interchanges (row_base + t) <-> piv[t0 + t], t < cnt, in order, on [c0, c1).
-__device__ void panel_swaps(double2 *__restrict__ A, int ldg, int row_base, int t0, int cnt,
-                            int c0, int c1, const PanelShared &sh) {
-  for (int j = c0 + threadIdx.x; j < c1; j += PT) {
-    for (int t = 0; t < cnt; ++t) {
-      const int c = row_base + t, p = sh.piv[t0 + t];
-      if (p != c) {
-        double2 *ec = A + (long long)c * ldg + j;
-        double2 *ep = A + (long long)p * ldg + j;
-        const double2 tmp = *ec;
-        *ec = *ep;
-        *ep = tmp;
-      }
-    }
-  }
-}
-
+// One workgroup per matrix.  Thread tid owns rows K0 + tid + s PT (s < RPT) for
+// the whole panel.  The panel is factored in column blocks of width W:
+//   1. the block's rows >= k0 are loaded into registers (v) and its W columns
+//      are eliminated there: pivot search among rows < N (border rows never
+//      pivot), the pivot row broadcast through LDS, rank-1 updates in registers;
+//   2. the block is stored, and its interchanges are applied to the panel
+//      columns left and right of it in one pass through LDS (net row moves);
+//   3. the block's U rows on the columns to its right are solved with its unit
+//      lower diagonal block (one thread per column, in registers);
+//   4. every thread applies the rank-W update to its own rows of those
+//      columns, with the block's L values still in its registers.
 template <int RPT, int W>
 __global__ void __launch_bounds__(PT, 1)
 lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0,
                 int *__restrict__ piv_g, int *__restrict__ moves_g, double2 *__restrict__ linv_g,
                 int *__restrict__ status) {
+  static_assert(W <= WMAX, "column block wider than the shared buffers");
   __shared__ PanelShared sh;
   const int f = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -221,108 +128,220 @@ lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, in
     double2 v[RPT][W];
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
-      const int r = k0 + tid + s * PT;
+      const int r = K0 + tid + s * PT;
 #pragma unroll
       for (int j = 0; j < W; ++j)
-        v[s][j] = (r < n && j < kb) ? A[(long long)r * ldg + k0 + j] : make_double2(0.0, 0.0);
+        v[s][j] = (r >= k0 && r < n && j < kb) ? A[(long long)r * ldg + k0 + j]
+                                               : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int c = 0; c < W; ++c) {
       if (c < kb) {
-      const int rc = k0 + c;
-      double best = -1.0;
-      int bi = rc;
+        const int rc = k0 + c;
+        double best = -1.0;
+        int bi = rc;
 #pragma unroll
-      for (int s = 0; s < RPT; ++s) {
-        const int r = k0 + tid + s * PT;
-        if (r >= rc && r < N) {
-          const double m = fabs(v[s][c].x) + fabs(v[s][c].y);
-          if (m > best) { best = m; bi = r; }
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (lane == 0) { sh.red_v[wave] = best; sh.red_i[wave] = bi; }
-      __syncthreads();
-      // every thread reduces the wave maxima itself (same order, same result)
-      double bv = sh.red_v[0];
-      int p = sh.red_i[0];
-#pragma unroll
-      for (int w = 1; w < PNW; ++w)
-        if (sh.red_v[w] > bv || (sh.red_v[w] == bv && sh.red_i[w] < p)) { bv = sh.red_v[w]; p = sh.red_i[w]; }
-      if (tid == 0) sh.piv[rc - K0] = p;
-      // row rc lives in slot 0 of thread c, row p in slot sp of thread tp: the
-      // owner of p publishes the pivot row, the owner of rc its old content
-      const int tp = (p - k0) % PT, sp = (p - k0) / PT;
-      if (tid == tp) {
-#pragma unroll
-        for (int s = 0; s < RPT; ++s)
-          if (s == sp) {
-#pragma unroll
-            for (int j = 0; j < W; ++j) sh.prow[j] = v[s][j];
+        for (int s = 0; s < RPT; ++s) {
+          const int r = K0 + tid + s * PT;
+          if (r >= rc && r < N) {
+            const double m = fabs(v[s][c].x) + fabs(v[s][c].y);
+            if (m > best) { best = m; bi = r; }
           }
-      }
-      if (p != rc && tid == c) {
-#pragma unroll
-        for (int j = 0; j < W; ++j) sh.xbuf[0][j] = v[0][j];
-      }
-      __syncthreads();
-      if (tid == c) {
-#pragma unroll
-        for (int j = 0; j < W; ++j) v[0][j] = sh.prow[j];
-      }
-      if (p != rc && tid == tp) {
-#pragma unroll
-        for (int s = 0; s < RPT; ++s)
-          if (s == sp) {
-#pragma unroll
-            for (int j = 0; j < W; ++j) v[s][j] = sh.xbuf[0][j];
-          }
-      }
-      const double2 d = sh.prow[c];
-      double2 inv;
-      if (d.x == 0.0 && d.y == 0.0) {
-        if (tid == 0) sh.flags = 1;
-        inv = make_double2(0.0, 0.0);
-      } else {
-        inv = cinv(d);
-      }
-#pragma unroll
-      for (int s = 0; s < RPT; ++s) {
-        const int r = k0 + tid + s * PT;
-        if (r > rc && r < n) {
-          const double2 l = cmul(v[s][c], inv);
-          v[s][c] = l;
-#pragma unroll
-          for (int j = c + 1; j < W; ++j)
-            if (j < kb) v[s][j] = csub(v[s][j], cmul(l, sh.prow[j]));
         }
-      }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off);
+          const int oi = __shfl_xor(bi, off);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (lane == 0) { sh.red_v[wave] = best; sh.red_i[wave] = bi; }
+        __syncthreads();
+        // every thread reduces the wave maxima itself (same order, same result)
+        double bv = sh.red_v[0];
+        int p = sh.red_i[0];
+#pragma unroll
+        for (int w = 1; w < PNW; ++w)
+          if (sh.red_v[w] > bv || (sh.red_v[w] == bv && sh.red_i[w] < p)) { bv = sh.red_v[w]; p = sh.red_i[w]; }
+        if (tid == 0) sh.piv[rc - K0] = p;
+        // row rc is slot 0 of thread rc - K0 (rc - K0 < NBO <= PT); row p is
+        // slot sp of thread tp: the owner of p publishes the pivot row, the
+        // owner of rc its old content
+        const int tc = rc - K0;
+        const int tp = (p - K0) % PT, sp = (p - K0) / PT;
+        if (tid == tp) {
+#pragma unroll
+          for (int s = 0; s < RPT; ++s)
+            if (s == sp) {
+#pragma unroll
+              for (int j = 0; j < W; ++j) sh.prow[j] = v[s][j];
+            }
+        }
+        if (p != rc && tid == tc) {
+#pragma unroll
+          for (int j = 0; j < W; ++j) sh.xbuf[j] = v[0][j];
+        }
+        __syncthreads();
+        if (tid == tc) {
+#pragma unroll
+          for (int j = 0; j < W; ++j) v[0][j] = sh.prow[j];
+        }
+        if (p != rc && tid == tp) {
+#pragma unroll
+          for (int s = 0; s < RPT; ++s)
+            if (s == sp) {
+#pragma unroll
+              for (int j = 0; j < W; ++j) v[s][j] = sh.xbuf[j];
+            }
+        }
+        const double2 d = sh.prow[c];
+        double2 inv;
+        if (d.x == 0.0 && d.y == 0.0) {
+          if (tid == 0) sh.flags = 1;
+          inv = make_double2(0.0, 0.0);
+        } else {
+          inv = cinv(d);
+        }
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) {
+          const int r = K0 + tid + s * PT;
+          if (r > rc && r < n) {
+            const double2 l = cmul(v[s][c], inv);
+            v[s][c] = l;
+#pragma unroll
+            for (int j = c + 1; j < W; ++j)
+              if (j < kb) v[s][j] = csub(v[s][j], cmul(l, sh.prow[j]));
+          }
+        }
       }  // c < kb
     }
+    // 2. store the block; its interchanges as net row moves (content of row
+    //    bsrc goes to row bdst) over the panel columns outside the block
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
-      const int r = k0 + tid + s * PT;
-      if (r < n) {
+      const int r = K0 + tid + s * PT;
+      if (r >= k0 && r < n) {
 #pragma unroll
         for (int j = 0; j < W; ++j)
           if (j < kb) A[(long long)r * ldg + k0 + j] = v[s][j];
       }
     }
+    if (tid == 0) {
+      int cnt = 0;
+      for (int t = 0; t < kb; ++t) {
+        const int a = k0 + t, b = sh.piv[a - K0];
+        int ia = -1, ib = -1;
+        for (int i = 0; i < cnt; ++i) {
+          if (sh.brow[i] == a) ia = i;
+          if (sh.brow[i] == b) ib = i;
+        }
+        if (ia < 0) { sh.brow[cnt] = a; sh.bcont[cnt] = a; ia = cnt++; }
+        if (ib < 0) { sh.brow[cnt] = b; sh.bcont[cnt] = b; ib = cnt++; }
+        const int tmp = sh.bcont[ia];
+        sh.bcont[ia] = sh.bcont[ib];
+        sh.bcont[ib] = tmp;
+      }
+      int m = 0;
+      for (int i = 0; i < cnt; ++i)
+        if (sh.bcont[i] != sh.brow[i]) {
+          sh.bdst[m] = sh.brow[i];
+          sh.bsrc[m] = sh.bcont[i];
+          ++m;
+        }
+      sh.bcnt = m;
+    }
     __syncthreads();
-    // this block's interchanges on the rest of the panel
-    panel_swaps(A, ldg, k0, k0 - K0, kb, K0, k0, sh);
-    panel_swaps(A, ldg, k0, k0 - K0, kb, ke, kend, sh);
+    {
+      const int cnt = sh.bcnt, nl = k0 - K0, nc = nl + (kend - ke);
+      if (cnt > 0 && nc > 0) {
+        for (int idx = tid; idx < cnt * nc; idx += PT) {
+          const int i = idx / nc, cc = idx - i * nc;
+          const int col = cc < nl ? K0 + cc : ke + (cc - nl);
+          sh.u.blk.stage[i][cc] = A[(long long)sh.bsrc[i] * ldg + col];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < cnt * nc; idx += PT) {
+          const int i = idx / nc, cc = idx - i * nc;
+          const int col = cc < nl ? K0 + cc : ke + (cc - nl);
+          A[(long long)sh.bdst[i] * ldg + col] = sh.u.blk.stage[i][cc];
+        }
+      }
+    }
     __syncthreads();
     if (ke < kend) {
-      panel_trsm(A, ldg, k0, kb, ke, kend, sh);
-      panel_gemm(A, ldg, ke, n, ke, kend, k0, kb, sh);
+      // 3. U rows k0..ke of columns ke..kend: unit lower solve with the
+      //    diagonal block (rows k0..ke are slot 0 of threads k0-K0 .. ke-K0)
+      if (tid >= k0 - K0 && tid < ke - K0) {
+        const int i = tid - (k0 - K0);
+#pragma unroll
+        for (int t = 0; t < W; ++t) sh.lbb[i][t] = v[0][t];
+      }
       __syncthreads();
+      // one thread per column; the solved rows accumulate in the U buffer
+      for (int c = ke + tid; c < kend; c += PT) {
+        double2 *uc = &sh.u.blk.U[0][c - ke];
+        for (int i = 0; i < kb; ++i) uc[i * NBO] = A[(long long)(k0 + i) * ldg + c];
+#pragma unroll 1
+        for (int i = 1; i < kb; ++i) {
+          double2 x = uc[i * NBO];
+          for (int t = 0; t < i; ++t) x = csub(x, cmul(sh.lbb[i][t], uc[t * NBO]));
+          uc[i * NBO] = x;
+        }
+        for (int i = 0; i < kb; ++i) A[(long long)(k0 + i) * ldg + c] = uc[i * NBO];
+      }
+      __syncthreads();
+      // 4. rank-kb update of rows ke..n on columns ke..kend (at most 4 tiles of
+      //    16 columns) on MFMA, without barriers: each wave takes 16-row
+      //    stripes; L from the block just stored, U from LDS.  The MFMA
+      //    layouts: A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16].
+      const int li = lane & 15, lk = lane >> 4;
+      const int nct = (kend - ke + 15) / 16;
+#pragma unroll 1
+      for (int r0 = ke + 16 * wave; r0 < n; r0 += 16 * PNW) {
+        d4 cre[4], cim[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          const int col = ke + 16 * ct + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = r0 + 4 * r + lk;
+            double2 x = make_double2(0.0, 0.0);
+            if (ct < nct && row < n && col < kend) x = A[(long long)row * ldg + col];
+            cre[ct][r] = x.x;
+            cim[ct][r] = x.y;
+          }
+        }
+#pragma unroll
+        for (int kk = 0; kk < W; kk += 4) {
+          if (kk < kb) {
+            const int row = r0 + li, k = kk + lk;
+            const double2 lv = (row < n && k < kb) ? A[(long long)row * ldg + k0 + k]
+                                                   : make_double2(0.0, 0.0);
+            const double ar = -lv.x, ai = -lv.y;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+              if (ct < nct) {
+                const double2 uv = k < kb ? sh.u.blk.U[k][16 * ct + li] : make_double2(0.0, 0.0);
+                cre[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.x, cre[ct], 0, 0, 0);
+                cre[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, uv.y, cre[ct], 0, 0, 0);
+                cim[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.y, cim[ct], 0, 0, 0);
+                cim[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, uv.x, cim[ct], 0, 0, 0);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          const int col = ke + 16 * ct + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = r0 + 4 * r + lk;
+            if (ct < nct && row < n && col < kend)
+              A[(long long)row * ldg + col] = make_double2(cre[ct][r], cim[ct][r]);
+          }
+        }
+      }
     }
+    __syncthreads();
   }
 
   if (tid < kbo) piv_g[(long long)f * NBO + tid] = sh.piv[tid];
@@ -561,14 +580,15 @@ void launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, i
   const int fgroups = (F + NXCD - 1) / NXCD;
   for (int K0 = 0; K0 < N; K0 += NBO) {
     const int kend = min(K0 + NBO, N);
-    if (rpt <= 1) launch_panel<1, 16>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    // register block v[RPT][W] kept at <= 128 VGPRs
+    if (rpt <= 1) launch_panel<1, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
     else if (rpt <= 2) launch_panel<2, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
     else if (rpt <= 3) launch_panel<3, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
     else if (rpt <= 4) launch_panel<4, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    else if (rpt <= 6) launch_panel<6, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    else if (rpt <= 6) launch_panel<6, 4>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
     else if (rpt <= 8) launch_panel<8, 4>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
     else if (rpt <= 12) launch_panel<12, 2>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    else if (rpt <= 16) launch_panel<16, 2>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
+    else if (rpt <= 16) launch_panel<16, 1>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
     else launch_panel<24, 1>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
     const int rem = n - kend;  // >= R >= 1
     const int nch = (rem + SW - 1) / SW;
