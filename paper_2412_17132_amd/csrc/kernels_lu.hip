@@ -38,10 +38,6 @@ constexpr int PT = 512;                     // panel threads
 constexpr int PNW = PT / 64;
 constexpr int MAX_MOVES = 2 * NBO;
 constexpr int SW = 16;                      // trailing columns per swap/U12 workgroup
-#ifndef GWC_LU_KCH
-#define GWC_LU_KCH 16
-#endif
-constexpr int KCH = GWC_LU_KCH;             // K chunk of the trailing update staged in LDS
 constexpr int NXCD = 8;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -458,12 +454,12 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
 }
 
 // ===========================================================================
-// G: trailing update A22 -= L21 U12, one 64 x 64 tile per workgroup.
+// G: trailing update A22 -= L21 U12, one 64 x 64 tile per workgroup; the MFMA
+// operands come straight from memory (the panels of one matrix are shared in
+// its XCD's L2), so the K loop has no barriers.
 __global__ void __launch_bounds__(256, 4)
 lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0, int F,
                    int mt) {
-  __shared__ double2 Ls[64][KCH + 1];
-  __shared__ double2 Us[KCH][64 + 1];
   int f, tile;
   if (!xcd_map(blockIdx.x, mt * mt, F, f, tile)) return;
   const int n = N + R;
@@ -491,36 +487,31 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
         cim[a][b][r] = v.y;
       }
     }
-  for (int kc = 0; kc < kbo; kc += KCH) {
-    const int kw = min(KCH, kbo - kc);
+#pragma unroll 4
+  for (int kk = 0; kk < kbo; kk += 4) {
+    const int k = kk + lk;
+    double2 lv[2], uv[2];
 #pragma unroll
-    for (int it = 0; it < (64 * KCH) / 256; ++it) {
-      const int idx = it * 256 + tid;
-      const int r = idx / KCH, t = idx - r * KCH;
-      Ls[r][t] = (ra + r < n && t < kw) ? A[(long long)(ra + r) * ldg + K0 + kc + t]
-                                        : make_double2(0.0, 0.0);
-      const int t2 = idx / 64, j = idx - t2 * 64;
-      Us[t2][j] = (t2 < kw && ca + j < n) ? A[(long long)(K0 + kc + t2) * ldg + ca + j]
-                                          : make_double2(0.0, 0.0);
+    for (int a = 0; a < 2; ++a) {
+      const int row = ra + wr + 16 * a + li;
+      lv[a] = (row < n && k < kbo) ? A[(long long)row * ldg + K0 + k] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < KCH; kk += 4) {
+    for (int b = 0; b < 2; ++b) {
+      const int col = ca + wc + 16 * b + li;
+      uv[b] = (k < kbo && col < n) ? A[(long long)(K0 + k) * ldg + col] : make_double2(0.0, 0.0);
+    }
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const double2 lv = Ls[wr + 16 * a + li][kk + lk];
-        const double ar = -lv.x, ai = -lv.y;
+    for (int a = 0; a < 2; ++a) {
+      const double ar = -lv[a].x, ai = -lv[a].y;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const double2 uv = Us[kk + lk][wc + 16 * b + li];
-          cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.x, cre[a][b], 0, 0, 0);
-          cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, uv.y, cre[a][b], 0, 0, 0);
-          cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.y, cim[a][b], 0, 0, 0);
-          cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, uv.x, cim[a][b], 0, 0, 0);
-        }
+      for (int b = 0; b < 2; ++b) {
+        cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv[b].x, cre[a][b], 0, 0, 0);
+        cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[a].y, uv[b].y, cre[a][b], 0, 0, 0);
+        cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv[b].y, cim[a][b], 0, 0, 0);
+        cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, uv[b].x, cim[a][b], 0, 0, 0);
       }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
