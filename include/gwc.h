@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define GWC_VERSION 10000 /* 1.0.0 */
+#define GWC_VERSION 10100 /* 1.1.0 */
 
 enum gwc_status {
   GWC_OK = 0,
@@ -48,8 +48,10 @@ enum gwc_mode {
    * (Eqs. cd_terms, cd_imaginary, cd_residue, cd_prefactors). */
   GWC_MODE_FULL = 0,
   /* Decoupling approximation (Eq. cd_sigma_imaginary_decoupled): on the grid
-   * only the m = n residue, giving Im Sigma^dec; Sigma^c_n(eps_n) is still
-   * computed with every term for the quasiparticle energy. */
+   * only the residues of n's equivalent set (m = n, or the symmetry-equivalent
+   * core levels given by sym_group, Eq. sigma_spectral_decoupled_symmetric),
+   * giving Im Sigma^dec; Sigma^c_n(eps_n) is still computed with every term
+   * for the quasiparticle energy. */
   GWC_MODE_DECOUPLED = 1
 };
 
@@ -87,7 +89,13 @@ typedef struct {
  *   vxc        [n_core] or NULL  <n|v_xc|n>, NULL means 0
  *   mode       enum gwc_mode
  *   precision  enum gwc_precision: the Pi builds (both axes) in that form; chi(z),
- *              the LU of 1 - Pi, the residue sums and E_QP stay FP64 */
+ *              the LU of 1 - Pi, the residue sums and E_QP stay FP64
+ *   sym_group  [n_basis] or NULL  labels of symmetry-equivalent core levels
+ *              (Eq. sigma_spectral_decoupled_symmetric): the equivalent set of a
+ *              core state n is every orbital carrying n's label when that label
+ *              is >= 0, else {n}; NULL means {n} for every n.  A set must hold
+ *              occupied orbitals only (GWC_ERR_INVALID_ARG otherwise).  It
+ *              selects the residues of Im Sigma^dec. */
 typedef struct {
   int32_t n_core;
   const int32_t *core_idx;
@@ -100,13 +108,16 @@ typedef struct {
   const double *vxc;
   int32_t mode;
   int32_t precision;
+  const int32_t *sym_group;
 } gwc_sigma_args;
 
 /* Outputs of gwc_sigma_core (each may be host or device memory).
  *   sigma_c      [n_core][n_real][2]  Sigma^c_n(w) = -I_n(w) + R_n(w) as (re, im);
  *                                     required in FULL mode, ignored (may be NULL)
  *                                     in DECOUPLED mode
- *   im_sigma_dec [n_core][n_real]     f_n Im W^c_nn(|eps_n - w| + i eta), or NULL
+ *   im_sigma_dec [n_core][n_real]     sum over n's equivalent set S of
+ *                                     f_i Im W^c_ni(|eps_i - w| + i eta), in ascending
+ *                                     i (S = {n} by default), or NULL
  *   sigma_c_eps  [n_core][2]          Sigma^c_n(eps_n) (re, im), or NULL
  *   sigma_x      [n_core]             Sigma^x_n = -sum_i (n i|i n), or NULL
  *   e_qp         [n_core]             E_QP = eps_n + Sigma^x_n + Re Sigma^c_n(eps_n) - v^xc_n

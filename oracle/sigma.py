@@ -166,23 +166,50 @@ def exchange(M_oo: np.ndarray, n: int) -> float:
     return float(-np.sum(M_oo[:, n, :] ** 2))
 
 
-def sigma_c_at(L, delta, eps, occ, M_oo, M_ov, n, omega, eta, Wn, omega_imag, w_imag):
+def equivalent_set(n: int, sym_group, n_occ: int) -> list:
+    """The symmetry-equivalent core levels of n (Eq.
+    sigma_spectral_decoupled_symmetric): every orbital whose label in sym_group
+    equals n's non-negative label, in ascending order; just [n] when sym_group is
+    None or n's label is negative.  The set must be occupied."""
+    if sym_group is None or int(sym_group[n]) < 0:
+        return [int(n)]
+    g = int(sym_group[n])
+    out = [m for m in range(len(sym_group)) if int(sym_group[m]) == g]
+    if any(m >= n_occ for m in out):
+        raise ValueError("an equivalent set must contain occupied orbitals only")
+    return out
+
+
+def im_decoupled(terms: dict, sym: list) -> float:
+    """Decoupled Im Sigma^c_n(omega) = sum_{i in Sym(n)} f_i Im W^c_ni(|eps_i - omega|
+    + i eta) (Eqs. cd_sigma_imaginary_decoupled, sigma_spectral_decoupled_symmetric),
+    summed in ascending i from the residue terms f_i W^c_ni."""
+    total = 0.0
+    for m in sym:
+        if m in terms:
+            total += float(np.imag(terms[m]))
+    return total
+
+
+def sigma_c_at(L, delta, eps, occ, M_oo, M_ov, n, omega, eta, Wn, omega_imag, w_imag, sym=None):
     """Sigma^c_n(omega) = -I_n(omega) + R_n(omega) (Eq. cd_terms) and the decoupled
-    imaginary part f_n Im W^c_nn(|eps_n - omega| + i eta) (Eq.
-    cd_sigma_imaginary_decoupled).  Returns (sigma_c, im_sigma_dec, terms)."""
+    imaginary part over the equivalent set `sym` (default [n]; Eqs.
+    cd_sigma_imaginary_decoupled, sigma_spectral_decoupled_symmetric).
+    Returns (sigma_c, im_sigma_dec, terms)."""
     I = imag_integral(Wn, eps, omega_imag, w_imag, omega)
     R, terms = residue(L, delta, eps, occ, M_oo, M_ov, n, omega, eta)
-    im_dec = float(np.imag(terms[n])) if n in terms else 0.0
+    im_dec = im_decoupled(terms, [n] if sym is None else sym)
     return -I + R, im_dec, terms
 
 
 def sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_real, eta,
-               vxc=None, mode: str = "full"):
+               vxc=None, mode: str = "full", sym_group=None):
     """Full oracle for the `gwc_sigma_core` entry point.
 
     mode "full": Sigma^c_n on every real grid point (all residue terms);
-    mode "decoupled": only the m = n residue on the grid (gives ImSigma^dec),
-    plus the full Sigma^c_n(eps_n) for E_QP.  Returns a dict with sigma_c
+    mode "decoupled": only the residues of n's equivalent set on the grid
+    (gives ImSigma^dec; the set is [n] unless sym_group labels equivalent core
+    levels), plus the full Sigma^c_n(eps_n) for E_QP.  Returns a dict with sigma_c
     [n_core][n_real] complex (None in decoupled mode), im_sigma_dec
     [n_core][n_real], sigma_c_eps [n_core] complex, sigma_x, e_qp [n_core]."""
     eps = np.asarray(eps, dtype=float)
@@ -202,16 +229,17 @@ def sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_real, e
     sigma_x = np.zeros(len(cores))
     e_qp = np.zeros(len(cores))
     for c, n in enumerate(cores):
+        sym = equivalent_set(n, sym_group, n_occ)
         for j in range(n_real):
             w = float(omega_real[c, j])
             if mode == "full":
                 s, d, _ = sigma_c_at(L, delta, eps, occ, M_oo, M_ov, n, w, eta, W[c],
-                                     omega_imag, w_imag)
+                                     omega_imag, w_imag, sym=sym)
                 sigma_c[c, j] = s
                 im_dec[c, j] = d
             else:
-                _, terms = residue(L, delta, eps, occ, M_oo, M_ov, n, w, eta, m_subset=[n])
-                im_dec[c, j] = float(np.imag(terms[n])) if n in terms else 0.0
+                _, terms = residue(L, delta, eps, occ, M_oo, M_ov, n, w, eta, m_subset=sym)
+                im_dec[c, j] = im_decoupled(terms, sym)
         s_eps, _, _ = sigma_c_at(L, delta, eps, occ, M_oo, M_ov, n, float(eps[n]), eta, W[c],
                                  omega_imag, w_imag)
         sigma_c_eps[c] = s_eps
@@ -221,23 +249,26 @@ def sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_real, e
                 sigma_x=sigma_x, e_qp=e_qp, w_imag=W)
 
 
-def sigma_core_system(sys, mode: str = "full"):
+def sigma_core_system(sys, mode: str = "full", sym_group=None):
     """Convenience wrapper taking an object with the ABI's fields as attributes."""
     return sigma_core(sys.eps, sys.occ, sys.M_oo, sys.M_ov, sys.core_idx, sys.omega_imag,
                       sys.w_imag, sys.omega_real, sys.eta, vxc=getattr(sys, "vxc", None),
-                      mode=mode)
+                      mode=mode, sym_group=sym_group)
 
 
-def count_residue_tasks(eps, occ, core_idx, omega_real, mode: str = "full") -> int:
+def count_residue_tasks(eps, occ, core_idx, omega_real, mode: str = "full",
+                        sym_group=None) -> int:
     """Number of (n, w, m) residue terms the path evaluates (grid plus w = eps_n)."""
     total = 0
+    n_occ = int(np.sum(np.asarray(occ) > 0))
     omega_real = np.asarray(omega_real).reshape(len(core_idx), -1)
     for c, n in enumerate(core_idx):
         n = int(n)
+        sym = equivalent_set(n, sym_group, n_occ)
         for w in omega_real[c]:
             if mode == "full":
                 total += len(residue_terms(eps, occ, float(w), 0.0))
             else:
-                total += len(residue_terms(eps, occ, float(w), 0.0, m_subset=[n]))
+                total += len(residue_terms(eps, occ, float(w), 0.0, m_subset=sym))
         total += len(residue_terms(eps, occ, float(eps[n]), 0.0))
     return total

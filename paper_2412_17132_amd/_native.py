@@ -61,6 +61,7 @@ class GwcSigmaArgs(Structure):
         ("n_real", c_int32), ("omega_real", c_void_p),
         ("eta", c_double), ("vxc", c_void_p),
         ("mode", c_int32), ("precision", c_int32),
+        ("sym_group", c_void_p),
     ]
 
 

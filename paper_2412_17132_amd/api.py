@@ -60,9 +60,10 @@ def _alloc(shape, like):
 
 def gwc_sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_real, eta,
                    vxc=None, mode: str = "full", precision: str = "fp64",
-                   out: Optional[dict] = None, stream=None) -> dict:
+                   out: Optional[dict] = None, stream=None, sym_group=None) -> dict:
     """Sigma^c_n(w) of the core states by contour deformation (gwc_sigma_core).
 
+    sym_group: optional [n_basis] int32 labels of symmetry-equivalent core levels.
     Returns a dict with sigma_c [n_core][n_real][2] (None in decoupled mode),
     im_sigma_dec [n_core][n_real], sigma_c_eps [n_core][2], sigma_x, e_qp."""
     lib = N.load()
@@ -76,7 +77,7 @@ def gwc_sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_rea
     args = N.GwcSigmaArgs(n_core, _as_arg(core_idx, "i4", keep), n_imag,
                           _as_arg(omega_imag, "f8", keep), _as_arg(w_imag, "f8", keep), n_real,
                           _as_arg(omega_real, "f8", keep), float(eta), _as_arg(vxc, "f8", keep),
-                          N.MODES[mode], N.PRECISIONS[precision])
+                          N.MODES[mode], N.PRECISIONS[precision], _as_arg(sym_group, "i4", keep))
     if out is None:
         out = {
             "sigma_c": _alloc((n_core, n_real, 2), M_ov) if mode == "full" else None,

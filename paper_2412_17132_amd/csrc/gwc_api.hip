@@ -482,10 +482,11 @@ void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, c
 struct SigmaInputs {
   std::vector<int> core;
   std::vector<double> wi, wwi, wr, vxc;
+  std::vector<std::vector<int>> sym;  // per core: its equivalent set, ascending
 };
 
-SigmaInputs check_sigma_args(int n_occ, const gwc_sigma_args *args, const gwc_sigma_out *out,
-                             hipStream_t s) {
+SigmaInputs check_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
+                             const gwc_sigma_out *out, hipStream_t s) {
   if (!args) fail(GWC_ERR_INVALID_ARG, "NULL args");
   const int nc = args->n_core, ni = args->n_imag, nr = args->n_real;
   if (nc < 1 || ni < 1 || nr < 1) fail(GWC_ERR_SHAPE, "n_core, n_imag, n_real must be >= 1");
@@ -521,28 +522,46 @@ SigmaInputs check_sigma_args(int n_occ, const gwc_sigma_args *args, const gwc_si
       if (!(in.wr[(size_t)c * nr + j] > in.wr[(size_t)c * nr + j - 1]))
         fail(GWC_ERR_INVALID_ARG, "omega_real of core %d must increase", c);
   if (!(args->eta > 0.0)) fail(GWC_ERR_INVALID_ARG, "eta must be > 0");
+  std::vector<int> labels;
+  if (args->sym_group) labels = to_host(args->sym_group, n_basis, s);
+  in.sym.resize(nc);
+  for (int c = 0; c < nc; ++c) {
+    const int n = in.core[c];
+    if (labels.empty() || labels[n] < 0) {
+      in.sym[c].push_back(n);
+      continue;
+    }
+    for (int m = 0; m < n_basis; ++m)
+      if (labels[m] == labels[n]) {
+        if (m >= n_occ) fail(GWC_ERR_INVALID_ARG, "equivalent set of core %d holds unoccupied orbital %d", n, m);
+        in.sym[c].push_back(m);
+      }
+  }
   return in;
 }
 
 // Residue tasks, ordered by (core, point, m); point n_real is w = eps_n.
+// dec[t] marks the tasks of the equivalent set (the terms of Im Sigma^dec).
 void build_residue_tasks(const ResidentSystem &rs, const gwc_sigma_args *args, const SigmaInputs &in,
                          TaskList &tr, std::vector<double> &ftask, std::vector<int> &cj_off,
-                         std::vector<int> &cj_self) {
+                         std::vector<int> &dec) {
   const int nc = args->n_core, nr = args->n_real, npts = nr + 1;
   const bool full = args->mode == GWC_MODE_FULL;
   cj_off.assign((size_t)nc * npts + 1, 0);
-  cj_self.assign((size_t)nc * npts, -1);
+  std::vector<char> in_set(rs.nb);
   for (int c = 0; c < nc; ++c) {
     const int nst = in.core[c];
+    std::fill(in_set.begin(), in_set.end(), 0);
+    for (int m : in.sym[c]) in_set[m] = 1;
     for (int j = 0; j < npts; ++j) {
       const double w = (j < nr) ? in.wr[(size_t)c * nr + j] : rs.eps[nst];
       const size_t cj = (size_t)c * npts + j;
       cj_off[cj] = (int)tr.size();
       for (int m = 0; m < rs.nb; ++m) {
-        if (!full && j < nr && m != nst) continue;
+        if (!full && j < nr && !in_set[m]) continue;
         const double f = prefactor(rs.eps[m], m < rs.no, w);
         if (f == 0.0) continue;
-        if (m == nst) cj_self[cj] = (int)tr.size();
+        dec.push_back(in_set[m]);
         tr.z.push_back(make_double2(std::fabs(rs.eps[m] - w), args->eta));
         tr.n.push_back(nst);
         tr.m.push_back(m);
@@ -557,18 +576,20 @@ void build_residue_tasks(const ResidentSystem &rs, const gwc_sigma_args *args, c
 
 }  // namespace
 
-void validate_sigma_args(int n_occ, const gwc_sigma_args *args, const gwc_sigma_out *out,
-                         hipStream_t s) {
-  (void)check_sigma_args(n_occ, args, out, s);
+void validate_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
+                         const gwc_sigma_out *out, hipStream_t s) {
+  (void)check_sigma_args(n_occ, n_basis, args, out, s);
 }
 
 size_t predict_sigma_bytes(const ResidentSystem &rs, const gwc_sigma_args *args, size_t batch_bytes) {
   if (batch_bytes == 0) batch_bytes = default_batch_bytes();
   const int nc = std::max(args->n_core, 1), nr = std::max(args->n_real, 1), ni = std::max(args->n_imag, 1);
   // residue task count bounded without reading the grids: every orbital at
-  // every point (FULL), or one per point plus every orbital at eps_n (DECOUPLED)
+  // every point (FULL), or the equivalent set (at most every occupied orbital)
+  // per point plus every orbital at eps_n (DECOUPLED)
+  const size_t per_point = args->sym_group ? (size_t)rs.no : 1;
   const size_t t_real = args->mode == GWC_MODE_FULL ? (size_t)nc * (nr + 1) * rs.nb
-                                                    : (size_t)nc * ((size_t)nr + rs.nb);
+                                                    : (size_t)nc * ((size_t)nr * per_point + rs.nb);
   const BatchPlan pi = plan_batch(rs, (size_t)ni * nc, rs.nb, batch_bytes);
   const BatchPlan pr = plan_batch(rs, t_real, 1, batch_bytes);
   const size_t fixed = (size_t)nc * rs.nb * ni * sizeof(double2) + t_real * (sizeof(double2) + sizeof(double)) +
@@ -579,7 +600,7 @@ size_t predict_sigma_bytes(const ResidentSystem &rs, const gwc_sigma_args *args,
 void run_sigma(ResidentSystem &rs, const gwc_sigma_args *args, gwc_sigma_out *out, hipStream_t s,
                size_t batch_bytes) {
   if (!out) fail(GWC_ERR_INVALID_ARG, "NULL out");
-  const SigmaInputs in = check_sigma_args(rs.no, args, out, s);
+  const SigmaInputs in = check_sigma_args(rs.no, rs.nb, args, out, s);
   if (batch_bytes == 0) batch_bytes = default_batch_bytes();
   const int N = rs.N, nb = rs.nb;
   const int nc = args->n_core, ni = args->n_imag, nr = args->n_real;
@@ -614,8 +635,8 @@ void run_sigma(ResidentSystem &rs, const gwc_sigma_args *args, gwc_sigma_out *ou
   // ---- residues
   TaskList tr;
   std::vector<double> ftask;
-  std::vector<int> cj_off, cj_self;
-  build_residue_tasks(rs, args, in, tr, ftask, cj_off, cj_self);
+  std::vector<int> cj_off, tdec;
+  build_residue_tasks(rs, args, in, tr, ftask, cj_off, tdec);
   DevBuf dWr(s);
   dWr.alloc(std::max<size_t>(tr.size(), 1) * sizeof(double2));
   run_screening(rs, mx, args->precision, tr, 1, dWr.as<double2>(), status, s, batch_bytes);
@@ -632,12 +653,12 @@ void run_sigma(ResidentSystem &rs, const gwc_sigma_args *args, gwc_sigma_out *ou
                     nc, full ? npts : 1, dI.as<double>(), s);
   const double *d_f = upload(dft, ftask, s);
   const int *d_cjo = upload(dcjo, cj_off, s);
-  const int *d_cjs = upload(dcjs, cj_self, s);
+  const int *d_tdec = upload(dcjs, tdec, s);
   dsig.alloc((size_t)nc * nr * 2 * sizeof(double));
   dimd.alloc((size_t)nc * nr * sizeof(double));
   dse.alloc((size_t)nc * 2 * sizeof(double));
   deq.alloc((size_t)nc * sizeof(double));
-  launch_assemble(dWr.as<double2>(), d_f, nullptr, d_cjo, d_cjs, dI.as<double>(), nc, nr,
+  launch_assemble(dWr.as<double2>(), d_f, d_tdec, d_cjo, dI.as<double>(), nc, nr,
                   rs.d_eps.as<double>(), d_core, dsx.as<double>(), d_vxc, full ? 1 : 0,
                   dsig.as<double>(), dimd.as<double>(), dse.as<double>(), deq.as<double>(), s);
   HIPCHECK(hipGetLastError());
@@ -741,7 +762,7 @@ int gwc_sigma_core(const gwc_system *sys, const gwc_sigma_args *args, gwc_sigma_
     if (!sys || !args || !out) fail(GWC_ERR_INVALID_ARG, "NULL system, args or out");
     hipStream_t s = (hipStream_t)hip_stream;
     // argument checks that need no device come first
-    gwc::validate_sigma_args(sys->n_occ, args, out, s);
+    gwc::validate_sigma_args(sys->n_occ, sys->n_occ + sys->n_virt, args, out, s);
     std::unique_ptr<gwc::ResidentSystem> rs(gwc::create_resident(sys, s));
     gwc::run_sigma(*rs, args, out, s, 0);
     return GWC_OK;

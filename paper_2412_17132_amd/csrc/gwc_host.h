@@ -39,8 +39,8 @@ void run_sigma(ResidentSystem &rs, const gwc_sigma_args *args, gwc_sigma_out *ou
                size_t batch_bytes);
 
 // Host-side checks of the self-energy arguments (no device work).
-void validate_sigma_args(int n_occ, const gwc_sigma_args *args, const gwc_sigma_out *out,
-                         hipStream_t s);
+void validate_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
+                         const gwc_sigma_out *out, hipStream_t s);
 
 // Upper bound of the device bytes run_sigma allocates for these arguments
 // (besides the resident system), with the same batch budget.

@@ -65,8 +65,8 @@ void launch_quadrature(const double2 *W_imag, const double *eps, int n_basis,
                        const double *omega_imag, const double *w_imag, int n_imag,
                        const double *omega_real, int n_real, const int *core_idx, int n_core,
                        int grid_points, double *I_out, hipStream_t stream);
-void launch_assemble(const double2 *W_real, const double *f_task, const int *task_m,
-                     const int *cj_offset, const int *cj_self, const double *I, int n_core,
+void launch_assemble(const double2 *W_real, const double *f_task, const int *task_dec,
+                     const int *cj_offset, const double *I, int n_core,
                      int n_real, const double *eps, const int *core_idx, const double *sigma_x,
                      const double *vxc, int full, double *sigma_c, double *im_dec,
                      double *sigma_c_eps, double *e_qp, hipStream_t stream);

@@ -120,7 +120,7 @@ void launch_quadrature(const double2 *W_imag, const double *eps, int n_basis,
 // Residue sum and assembly, one thread per (core, point).  Tasks of a point
 // are contiguous and ordered by m, so the sum order is fixed.
 __global__ void assemble_kernel(const double2 *__restrict__ W_real, const double *__restrict__ f_task,
-                                const int *__restrict__ cj_offset, const int *__restrict__ cj_self,
+                                const int *__restrict__ cj_offset, const int *__restrict__ task_dec,
                                 const double *__restrict__ I, int n_core, int n_real,
                                 const double *__restrict__ eps, const int *__restrict__ core_idx,
                                 const double *__restrict__ sigma_x, const double *__restrict__ vxc,
@@ -130,13 +130,13 @@ __global__ void assemble_kernel(const double2 *__restrict__ W_real, const double
   const int npts = n_real + 1;
   if (cj >= n_core * npts) return;
   const int c = cj / npts, j = cj - c * npts;
-  double rr = 0.0, ri = 0.0;
+  // residue sum in m order; Im Sigma^dec over the equivalent set's terms
+  double rr = 0.0, ri = 0.0, imd = 0.0;
   for (int t = cj_offset[cj]; t < cj_offset[cj + 1]; ++t) {
     rr += f_task[t] * W_real[t].x;
     ri += f_task[t] * W_real[t].y;
+    if (task_dec[t]) imd += f_task[t] * W_real[t].y;
   }
-  const int ts = cj_self[cj];
-  const double imd = ts >= 0 ? f_task[ts] * W_real[ts].y : 0.0;
   if (j < n_real) {
     if (full) {
       const double Iv = I[(long long)c * npts + j];
@@ -153,13 +153,13 @@ __global__ void assemble_kernel(const double2 *__restrict__ W_real, const double
   }
 }
 
-void launch_assemble(const double2 *W_real, const double *f_task, const int * /*task_m*/,
-                     const int *cj_offset, const int *cj_self, const double *I, int n_core,
+void launch_assemble(const double2 *W_real, const double *f_task, const int *task_dec,
+                     const int *cj_offset, const double *I, int n_core,
                      int n_real, const double *eps, const int *core_idx, const double *sigma_x,
                      const double *vxc, int full, double *sigma_c, double *im_dec,
                      double *sigma_c_eps, double *e_qp, hipStream_t stream) {
   const int total = n_core * (n_real + 1);
-  assemble_kernel<<<(total + 63) / 64, 64, 0, stream>>>(W_real, f_task, cj_offset, cj_self, I,
+  assemble_kernel<<<(total + 63) / 64, 64, 0, stream>>>(W_real, f_task, cj_offset, task_dec, I,
                                                         n_core, n_real, eps, core_idx, sigma_x,
                                                         vxc, full, sigma_c, im_dec, sigma_c_eps,
                                                         e_qp);

@@ -143,3 +143,23 @@ def test_c2_size_sampled():
                                       W, s.omega_imag, s.w_imag)
         e_ref = s.eps[n] + OS.exchange(s.M_oo, n) + ref_eps.real
         assert abs(out["e_qp"][c] - e_ref) <= TOL * abs(e_ref)
+
+
+@pytest.mark.parametrize("mode", ["decoupled", "full"])
+def test_symmetric_decoupling(mode):
+    """Two degenerate core levels labelled equivalent: Im Sigma^dec sums both
+    residues (Eq. sigma_spectral_decoupled_symmetric); sym_group from host memory."""
+    s = system_from_config(small_config(n_occ=4, n_virt=9, n_aux=70, n_core=2, n_real=8, seed=93,
+                                        real_abs_ev=(-300.0, -280.0)))
+    s.eps = s.eps.copy()
+    s.eps[1] = s.eps[0]
+    sym = -np.ones(s.n_basis, dtype=np.int32)
+    sym[0] = sym[1] = 5
+    print(f"case symmetric decoupling mode={mode}", flush=True)
+    d = gwc.to_device(s, _dev())
+    out = gwc.gwc_sigma_core(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],
+                             d["omega_imag"], d["w_imag"], d["omega_real"], d["eta"], mode=mode,
+                             sym_group=sym)
+    torch.cuda.synchronize()
+    out = {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+    _compare(out, OS.sigma_core_system(s, mode=mode, sym_group=sym), mode)

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol(gwc):
     lib = ctypes.CDLL(_native.LIB_PATH)
     for name in decl:
         assert hasattr(lib, name), name
-    assert gwc.version() == 10000
+    assert gwc.version() == int(re.search(r"#define GWC_VERSION (\d+)", open(HEADER).read()).group(1))
 
 
 def _sys():
@@ -46,7 +46,7 @@ def _call(gwc, s, **kw):
 
 @pytest.mark.parametrize("case,status", [
     ("gap", -3), ("occ", -1), ("core", -2), ("eta", -1), ("grid_order", -1),
-    ("imag_weight", -1), ("nan_eps", -4), ("fp8", -8), ("mode", None),
+    ("imag_weight", -1), ("nan_eps", -4), ("fp8", -8), ("mode", None), ("sym_virtual", -1),
 ])
 def test_sigma_core_argument_errors(gwc, case, status):
     s = _sys()
@@ -67,6 +67,10 @@ def test_sigma_core_argument_errors(gwc, case, status):
         s.eps[5] = np.nan
     elif case == "fp8":
         kw["precision"] = "fp8"
+    elif case == "sym_virtual":
+        sym = -np.ones(s.n_basis, dtype=np.int32)
+        sym[0] = sym[s.n_occ] = 1  # an unoccupied orbital in the core's equivalent set
+        kw["sym_group"] = sym
     elif case == "mode":
         with pytest.raises(KeyError):
             _call(gwc, s, mode="bogus")

@@ -263,3 +263,51 @@ def test_eqp_is_hedin_shift_fixed_point():
     r = S.sigma_core_system(s)
     dH = r["sigma_x"][0] + r["sigma_c_eps"][0].real - s.vxc[0]
     assert r["e_qp"][0] == pytest.approx(s.eps[0] + dH, abs=1e-15)
+
+
+# --- symmetry-equivalent core levels ------------------------------------------
+
+def _equivalent_pair(seed=91):
+    s = _tiny(seed=seed, n_occ=4, n_virt=6, n_aux=14, n_core=2, n_real=6,
+              real_abs_ev=(-300.0, -280.0))
+    s.eps = s.eps.copy()
+    s.eps[1] = s.eps[0]  # two degenerate (symmetry-equivalent) core levels
+    sym = -np.ones(s.n_basis, dtype=np.int32)
+    sym[0] = sym[1] = 3
+    return s, sym
+
+
+def test_symmetric_decoupling_matches_pole_form():
+    """Eq. sigma_spectral_decoupled_symmetric in its CD form: the decoupled Im
+    Sigma of core n sums f_i Im W^c_ni(|eps_i - w| + i eta) over the equivalent
+    cores i; checked against the Casida spectral W of each pair (n, i)."""
+    s, sym = _equivalent_pair()
+    out = S.sigma_core_system(s, mode="decoupled", sym_group=sym)
+    Om, XpY = RF.casida_symmetric(s.eps, s.n_occ, s.M_ov)
+    for c, n in enumerate(s.core_idx):
+        rho = RF.transition_moments(s.M_oo, s.M_ov, int(n), XpY)
+        ref = np.zeros(s.omega_real.shape[1])
+        for j, w in enumerate(s.omega_real[c]):
+            for i in (0, 1):
+                f = S.prefactor(float(s.eps[i]), True, float(w))
+                if f != 0.0:
+                    ref[j] += f * RF.w_pole(rho[i], Om, abs(float(s.eps[i]) - w) + 1j * s.eta).imag
+        assert np.max(np.abs(out["im_sigma_dec"][c] - ref)) <= 1e-10 * np.max(np.abs(ref))
+        # the partner term is not negligible here: the set changes the result
+        plain = S.sigma_core_system(s, mode="decoupled")["im_sigma_dec"][c]
+        assert np.max(np.abs(plain - ref)) > 1e-3 * np.max(np.abs(ref))
+
+
+def test_symmetric_decoupling_defaults_and_full_mode():
+    s, sym = _equivalent_pair(seed=92)
+    none = S.sigma_core_system(s, mode="decoupled")
+    unlabeled = S.sigma_core_system(s, mode="decoupled", sym_group=-np.ones(s.n_basis, int))
+    assert np.array_equal(none["im_sigma_dec"], unlabeled["im_sigma_dec"])
+    full = S.sigma_core_system(s, mode="full", sym_group=sym)
+    dec = S.sigma_core_system(s, mode="decoupled", sym_group=sym)
+    assert np.array_equal(full["im_sigma_dec"], dec["im_sigma_dec"])
+    assert np.array_equal(full["e_qp"], dec["e_qp"])
+    bad = sym.copy()
+    bad[s.n_occ] = 3  # a virtual orbital in the set
+    with pytest.raises(ValueError):
+        S.sigma_core_system(s, mode="decoupled", sym_group=bad)
