@@ -83,8 +83,10 @@ def test_wac_decoupled_matches_full_and_windows():
             s.eta, p)
     full = WA.sigma_core_wac(*args, mode="full")
     dec = WA.sigma_core_wac(*args, mode="decoupled")
-    assert np.array_equal(full["e_qp"], dec["e_qp"])
-    # decoupled fits only the pairs it needs; the m = n fit uses the same nodes
+    # the valence windows differ between the modes (decoupled places them from the
+    # residues at eps_n only); W is smooth there, so E_QP agrees to rounding
+    assert np.allclose(full["e_qp"], dec["e_qp"], rtol=1e-10, atol=0)
+    # the m = n fit uses the same core-window nodes in both modes
     assert np.allclose(full["im_sigma_dec"], dec["im_sigma_dec"], rtol=0, atol=0)
     pairs, xc, xv = WA.windows(s.eps, s.occ, int(s.core_idx[0]), list(s.omega_real[0]), s.eta, p)
     assert pairs[int(s.core_idx[0])] == "core"
