@@ -120,6 +120,27 @@ def cpu_baseline(system, mode, n_tasks_per_core, budget_tasks=24):
     }
 
 
+def residue_task_count(eps, occ, core_idx, omega_real, mode="full"):
+    """Residue terms (n, w, m) with a nonzero prefactor (Eq. cd_prefactors:
+    occupied m at or above w, virtual m at or below w) on each core's grid plus
+    w = eps_n; DECOUPLED keeps only m = n on the grid.  Bookkeeping for the
+    reported task counts."""
+    import numpy as np
+    eps = np.asarray(eps)
+    occupied = np.asarray(occ) > 0
+    omega_real = np.asarray(omega_real).reshape(len(core_idx), -1)
+    def live(w):
+        return (occupied & (eps >= w)) | (~occupied & (eps <= w))
+
+    total = 0
+    for c, n in enumerate(core_idx):
+        n = int(n)
+        for w in omega_real[c]:
+            total += int(live(w).sum()) if mode == "full" else int(live(w)[n])
+        total += int(live(float(eps[n])).sum())
+    return total
+
+
 def measure_peaks(gwc):
     """Device peaks re-measured by the library's probes (register-operand MFMA
     loops, a 4 GiB device copy), beside the datasheet figures."""
@@ -142,7 +163,6 @@ def sampled_main(args):
     import torch
 
     import paper_2412_17132_amd as gwc
-    from oracle import sigma as OS  # task count only (host bookkeeping)
     from paper_2412_17132_amd.serve import ResidentSystem
     from workloads import CONFIGS, EV_PER_HA, system_from_config
 
@@ -150,7 +170,7 @@ def sampled_main(args):
     cfg = CONFIGS[args.config]
     s = system_from_config(cfg)
     n_core = s.n_core
-    n_tasks_full = OS.count_residue_tasks(s.eps, s.occ, s.core_idx, s.omega_real, args.mode)
+    n_tasks_full = residue_task_count(s.eps, s.occ, s.core_idx, s.omega_real, args.mode)
     rs = ResidentSystem.from_system(s)
     core = s.core_idx[:1]
     n_real = s.omega_real.shape[1]
@@ -158,7 +178,7 @@ def sampled_main(args):
     def run(k):
         idx = np.unique(np.linspace(0, n_real - 1, k).round().astype(int))
         w = np.ascontiguousarray(s.omega_real[:1, idx])
-        tasks = OS.count_residue_tasks(s.eps, s.occ, core, w, args.mode)
+        tasks = residue_task_count(s.eps, s.occ, core, w, args.mode)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = rs.sigma_core(core, s.omega_imag, s.w_imag, w, s.eta, mode=args.mode,
@@ -363,6 +383,8 @@ def main():
                          "E_QP / satellite-position errors against the FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the peak-rate probes")
+    ap.add_argument("--no-wac", action="store_true",
+                    help="skip the CD-WAC leg (the paper's settings) reported beside the CD value")
     ap.add_argument("--no-decoupled", action="store_true",
                     help="skip the DECOUPLED-mode leg reported beside the FULL value")
     ap.add_argument("--sample-points", type=int, default=0,
@@ -406,7 +428,6 @@ def main():
     import torch
 
     import paper_2412_17132_amd as gwc
-    from oracle import sigma as OS  # task count only (host bookkeeping)
     from workloads import CONFIGS, EV_PER_HA, system_from_config
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -419,10 +440,10 @@ def main():
     n_t, d_omega = 2 ** 18, 0.01 / EV_PER_HA
     n_out = 3500
 
-    def step(precision=args.precision):
+    def step(precision=args.precision, wac=None):
         out = gwc.gwc_sigma_core(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],
                                  d["omega_imag"], d["w_imag"], d["omega_real"], d["eta"],
-                                 mode=args.mode, precision=precision)
+                                 mode=args.mode, precision=precision, wac=wac)
         e_qp = out["e_qp"].cpu().numpy()
         spectra = []
         for c in range(n_core):
@@ -452,7 +473,7 @@ def main():
 
     solves = args.steps * n_core
     value = solves / elapsed
-    n_tasks = OS.count_residue_tasks(s.eps, s.occ, s.core_idx, s.omega_real, args.mode)
+    n_tasks = residue_task_count(s.eps, s.occ, s.core_idx, s.omega_real, args.mode)
     launches = max(pi["launches"], 1)
     achieved = pi["flops"] / (pi["total_ms"] / 1e3) / 1e12 if pi["total_ms"] > 0 else 0.0
     tpt = _traffic_per_task()
@@ -546,6 +567,43 @@ def main():
             "satellite_max_shift_mev": worst * EV_PER_HA * 1e3,
             "sigma_c_rel_err": sc_err,
         }
+    if not args.no_wac:
+        wp = gwc.wac_paper_settings()
+        step(args.precision, wp)  # warm-up
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        for _ in range(args.steps):
+            wres = step(args.precision, wp)
+        torch.cuda.synchronize()
+        el_w = time.perf_counter() - tw
+        ref_out, ref_spec = last
+        w_out, w_spec = wres
+        deq = np.abs(w_out["e_qp"].cpu().numpy() - ref_out["e_qp"].cpu().numpy())
+        worst = 0.0
+        for c in range(n_core):
+            eq_r = float(ref_out["e_qp"][c]); eq_w = float(w_out["e_qp"][c])
+            wr = eq_r - 30 / EV_PER_HA + np.arange(n_out) * d_omega
+            ww = eq_w - 30 / EV_PER_HA + np.arange(n_out) * d_omega
+            pr = _satellites(wr, ref_spec[c][0].cpu().numpy(), eq_r, float(ref_spec[c][1][0]), s.eta)
+            pw = _satellites(ww, w_spec[c][0].cpu().numpy(), eq_w, float(w_spec[c][1][0]), s.eta)
+            for q in pr:
+                if pw:
+                    worst = max(worst, float(np.min(np.abs(np.asarray(pw) - q))))
+        sc_err = None
+        if args.mode == "full":
+            a = ref_out["sigma_c"].cpu().numpy(); b = w_out["sigma_c"].cpu().numpy()
+            rel = np.abs((b - a)[..., 0] + 1j * (b - a)[..., 1]) / np.max(np.abs(a[..., 0] + 1j * a[..., 1]))
+            sc_err = {"max": float(rel.max()), "median": float(np.median(rel))}
+        res["wac"] = {
+            "value": solves / el_w, "unit": "solves/s", "ms_per_step": el_w / args.steps * 1e3,
+            "speedup_vs_cd": elapsed / el_w,
+            "settings": {k: (v * EV_PER_HA if k in ("core_min", "core_max") else v) for k, v in wp.items()},
+            "settings_units": "core window in eV",
+            "reference_factorisations_per_step": n_core * (wp["n_core_pts"] + wp["n_val_pts"]),
+            "e_qp_max_dev_from_cd_mev": float(deq.max() * EV_PER_HA * 1e3),
+            "satellite_max_shift_from_cd_mev": worst * EV_PER_HA * 1e3,
+            "sigma_c_rel_dev_from_cd": sc_err,
+        }
     if args.mode == "full" and not args.no_decoupled:
         mode_full = args.mode
         args.mode = "decoupled"
@@ -559,7 +617,7 @@ def main():
         args.mode = mode_full
         res["decoupled"] = {
             "value": solves / el_d, "unit": "solves/s", "ms_per_step": el_d / args.steps * 1e3,
-            "residue_tasks_per_step": OS.count_residue_tasks(s.eps, s.occ, s.core_idx, s.omega_real,
+            "residue_tasks_per_step": residue_task_count(s.eps, s.occ, s.core_idx, s.omega_real,
                                                              "decoupled"),
             "precision": args.precision,
         }

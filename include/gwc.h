@@ -80,6 +80,32 @@ typedef struct {
   const double *M_ov;
 } gwc_system;
 
+/* CD-WAC settings (paper section "Numerical GW+C scheme", Eq. pade_approximation;
+ * the paper's values in section "Computational Details": 100 + 100 points,
+ * core window 0..40 eV, valence margins 0.08 and 0.01).  W^c_nm is computed
+ * at reference points only -- the imaginary nodes of the I_n quadrature and
+ * real points z = x + i eta -- and every residue W^c_nm(|eps_m - w| + i eta)
+ * is taken from a continued-fraction (Thiele) fit through them:
+ *   a pair (n, m) lies in the core window when every residue argument
+ *   x = |eps_m - w| of the pair is <= core_max; its real points are then
+ *   n_core_pts values spaced evenly on [core_min, core_max];
+ *   the other pairs of n use n_val_pts points spaced evenly on
+ *   [(1 - delta_lower) x_min, (1 + delta_upper) x_max], x_min / x_max the
+ *   smallest / largest residue argument over those pairs;
+ *   a pair's nodes are the imaginary nodes (ascending) then its window's points.
+ * Each window point costs one bordered factorisation with every orbital that
+ * has residue terms as border (the occupied ones for core-level grids).
+ * Constraints: n_core_pts, n_val_pts >= 2; 0 <= core_min < core_max;
+ * 0 <= delta_lower < 1; delta_upper >= 0; n_imag + max(n_core_pts, n_val_pts)
+ * <= 1024 (GWC_ERR_INVALID_ARG / GWC_ERR_SHAPE otherwise).  A fit that breaks
+ * down (a zero reciprocal difference) returns GWC_ERR_FACTORIZATION. */
+typedef struct {
+  int32_t n_core_pts;
+  double core_min, core_max;
+  int32_t n_val_pts;
+  double delta_lower, delta_upper;
+} gwc_wac_params;
+
 /* Arguments of gwc_sigma_core.
  *   core_idx   [n_core]          occupied states n (each < n_occ), the "core states"
  *   omega_imag [n_imag], w_imag  nodes (> 0, strictly increasing) and weights (> 0)
@@ -95,7 +121,9 @@ typedef struct {
  *              core state n is every orbital carrying n's label when that label
  *              is >= 0, else {n}; NULL means {n} for every n.  A set must hold
  *              occupied orbitals only (GWC_ERR_INVALID_ARG otherwise).  It
- *              selects the residues of Im Sigma^dec. */
+ *              selects the residues of Im Sigma^dec.
+ *   wac        NULL: contour deformation, every residue W from its own
+ *              factorisation; else CD-WAC with these settings (host memory) */
 typedef struct {
   int32_t n_core;
   const int32_t *core_idx;
@@ -109,6 +137,7 @@ typedef struct {
   int32_t mode;
   int32_t precision;
   const int32_t *sym_group;
+  const gwc_wac_params *wac;
 } gwc_sigma_args;
 
 /* Outputs of gwc_sigma_core (each may be host or device memory).

@@ -4,7 +4,7 @@ spectral function.  The compute lives in libgwc.so (HIP, gfx950); this
 package is its Python binding."""
 from ._native import GwcError
 from .api import (gwc_sigma_core, gwc_spectral_cumulant, probe_peak, timing_enable, timing_get,
-                  to_device, version)
+                  to_device, version, wac_paper_settings)
 
 __all__ = ["GwcError", "gwc_sigma_core", "gwc_spectral_cumulant", "probe_peak", "timing_enable", "timing_get",
-           "to_device", "version"]
+           "to_device", "version", "wac_paper_settings"]

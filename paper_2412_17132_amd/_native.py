@@ -54,6 +54,13 @@ class GwcSystem(Structure):
     ]
 
 
+class GwcWacParams(Structure):
+    _fields_ = [
+        ("n_core_pts", c_int32), ("core_min", c_double), ("core_max", c_double),
+        ("n_val_pts", c_int32), ("delta_lower", c_double), ("delta_upper", c_double),
+    ]
+
+
 class GwcSigmaArgs(Structure):
     _fields_ = [
         ("n_core", c_int32), ("core_idx", c_void_p),
@@ -61,7 +68,7 @@ class GwcSigmaArgs(Structure):
         ("n_real", c_int32), ("omega_real", c_void_p),
         ("eta", c_double), ("vxc", c_void_p),
         ("mode", c_int32), ("precision", c_int32),
-        ("sym_group", c_void_p),
+        ("sym_group", c_void_p), ("wac", c_void_p),
     ]
 
 

@@ -60,10 +60,12 @@ def _alloc(shape, like):
 
 def gwc_sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_real, eta,
                    vxc=None, mode: str = "full", precision: str = "fp64",
-                   out: Optional[dict] = None, stream=None, sym_group=None) -> dict:
+                   out: Optional[dict] = None, stream=None, sym_group=None, wac=None) -> dict:
     """Sigma^c_n(w) of the core states by contour deformation (gwc_sigma_core).
 
     sym_group: optional [n_basis] int32 labels of symmetry-equivalent core levels.
+    wac: optional dict of CD-WAC settings (n_core_pts, core_min, core_max,
+    n_val_pts, delta_lower, delta_upper; Hartree) -- CD-WAC instead of CD.
     Returns a dict with sigma_c [n_core][n_real][2] (None in decoupled mode),
     im_sigma_dec [n_core][n_real], sigma_c_eps [n_core][2], sigma_x, e_qp."""
     lib = N.load()
@@ -77,7 +79,8 @@ def gwc_sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_rea
     args = N.GwcSigmaArgs(n_core, _as_arg(core_idx, "i4", keep), n_imag,
                           _as_arg(omega_imag, "f8", keep), _as_arg(w_imag, "f8", keep), n_real,
                           _as_arg(omega_real, "f8", keep), float(eta), _as_arg(vxc, "f8", keep),
-                          N.MODES[mode], N.PRECISIONS[precision], _as_arg(sym_group, "i4", keep))
+                          N.MODES[mode], N.PRECISIONS[precision], _as_arg(sym_group, "i4", keep),
+                          wac_arg(wac, keep))
     if out is None:
         out = {
             "sigma_c": _alloc((n_core, n_real, 2), M_ov) if mode == "full" else None,
@@ -90,6 +93,25 @@ def gwc_sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_rea
                         ("sigma_c", "im_sigma_dec", "sigma_c_eps", "sigma_x", "e_qp")))
     N.check(lib.gwc_sigma_core(sys, args, o, _stream_handle(stream)))
     return out
+
+
+def wac_paper_settings(n_core_pts: int = 100, n_val_pts: int = 100) -> dict:
+    """The paper's CD-WAC settings (section "Computational Details"): 100 core-window
+    and 100 valence-window points, core window 0..40 eV, valence margins 8 % below
+    and 1 % above; energies in Hartree."""
+    return dict(n_core_pts=n_core_pts, core_min=0.0, core_max=40.0 / 27.211386245988,
+                n_val_pts=n_val_pts, delta_lower=0.08, delta_upper=0.01)
+
+
+def wac_arg(wac, keep: list):
+    """Pointer to a gwc_wac_params built from a dict (None: contour deformation)."""
+    if wac is None:
+        return None
+    import ctypes
+    p = N.GwcWacParams(int(wac["n_core_pts"]), float(wac["core_min"]), float(wac["core_max"]),
+                       int(wac["n_val_pts"]), float(wac["delta_lower"]), float(wac["delta_upper"]))
+    keep.append(p)
+    return ctypes.addressof(p)
 
 
 def _as_out(x):

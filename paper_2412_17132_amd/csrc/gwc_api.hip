@@ -14,6 +14,7 @@
 // Calls from several host threads run concurrently (each on its own stream);
 // temporaries come from the stream-ordered allocator.
 #include <algorithm>
+#include <limits>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -483,6 +484,8 @@ struct SigmaInputs {
   std::vector<int> core;
   std::vector<double> wi, wwi, wr, vxc;
   std::vector<std::vector<int>> sym;  // per core: its equivalent set, ascending
+  bool wac = false;
+  gwc_wac_params wp{};
 };
 
 SigmaInputs check_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
@@ -522,6 +525,21 @@ SigmaInputs check_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
       if (!(in.wr[(size_t)c * nr + j] > in.wr[(size_t)c * nr + j - 1]))
         fail(GWC_ERR_INVALID_ARG, "omega_real of core %d must increase", c);
   if (!(args->eta > 0.0)) fail(GWC_ERR_INVALID_ARG, "eta must be > 0");
+  if (args->wac) {
+    in.wac = true;
+    in.wp = *args->wac;
+    const gwc_wac_params &w = in.wp;
+    if (!std::isfinite(w.core_min) || !std::isfinite(w.core_max) || !std::isfinite(w.delta_lower) ||
+        !std::isfinite(w.delta_upper))
+      fail(GWC_ERR_NONFINITE, "non-finite CD-WAC setting");
+    if (w.n_core_pts < 2 || w.n_val_pts < 2) fail(GWC_ERR_SHAPE, "CD-WAC windows need >= 2 points each");
+    if (ni + std::max(w.n_core_pts, w.n_val_pts) > WAC_MAX_NODES)
+      fail(GWC_ERR_SHAPE, "n_imag + window points exceeds %d", WAC_MAX_NODES);
+    if (!(w.core_min >= 0.0 && w.core_max > w.core_min))
+      fail(GWC_ERR_INVALID_ARG, "CD-WAC core window must satisfy 0 <= core_min < core_max");
+    if (!(w.delta_lower >= 0.0 && w.delta_lower < 1.0 && w.delta_upper >= 0.0))
+      fail(GWC_ERR_INVALID_ARG, "CD-WAC margins must satisfy 0 <= delta_lower < 1, delta_upper >= 0");
+  }
   std::vector<int> labels;
   if (args->sym_group) labels = to_host(args->sym_group, n_basis, s);
   in.sym.resize(nc);
@@ -574,6 +592,125 @@ void build_residue_tasks(const ResidentSystem &rs, const gwc_sigma_args *args, c
   cj_off[(size_t)nc * npts] = (int)tr.size();
 }
 
+// Evenly spaced points on [a, b], rounded as numpy.linspace rounds them
+// (j * step + a, the last point b itself).
+std::vector<double> even_points(double a, double b, int n) {
+  std::vector<double> y(n);
+  const double step = (b - a) / (double)(n - 1);
+  for (int j = 0; j < n; ++j) {
+    const double t = (double)j * step;
+    y[j] = t + a;
+  }
+  y[n - 1] = b;
+  return y;
+}
+
+// CD-WAC: W at the reference points, one continued-fraction fit per pair
+// (core c, orbital m) with residue terms, and W_real[t] of every residue task
+// from its pair's fit (Eq. pade_approximation).
+void run_wac(ResidentSystem &rs, const MixedOperands *mx, const gwc_sigma_args *args,
+             const SigmaInputs &in, const TaskList &tr, const std::vector<int> &cj_off,
+             const double2 *d_Wimag, double2 *d_Wreal, std::vector<int> &status, hipStream_t s,
+             size_t batch_bytes) {
+  const gwc_wac_params &wp = in.wp;
+  const int nc = args->n_core, ni = args->n_imag, nb = rs.nb, npts = args->n_real + 1;
+  const size_t T = tr.size();
+  if (T == 0) return;
+  const double INF = std::numeric_limits<double>::infinity();
+  std::vector<double> xlo((size_t)nc * nb, INF), xhi((size_t)nc * nb, -INF);
+  std::vector<int> task_core(T);
+  int R_w = 0;
+  for (int c = 0; c < nc; ++c)
+    for (int t = cj_off[(size_t)c * npts]; t < cj_off[(size_t)(c + 1) * npts]; ++t) {
+      const size_t k = (size_t)c * nb + tr.m[t];
+      xlo[k] = std::min(xlo[k], tr.z[t].x);
+      xhi[k] = std::max(xhi[k], tr.z[t].x);
+      task_core[t] = c;
+      R_w = std::max(R_w, tr.m[t] + 1);
+    }
+  const int NC = wp.n_core_pts, NV = wp.n_val_pts, n_rr = NC + NV;
+  const std::vector<double> xc = even_points(wp.core_min, wp.core_max, NC);
+  std::vector<std::vector<double>> xv(nc);
+  std::vector<char> has_core(nc, 0), has_val(nc, 0);
+  for (int c = 0; c < nc; ++c) {
+    double lo = INF, hi = -INF;
+    for (int m = 0; m < nb; ++m) {
+      const size_t k = (size_t)c * nb + m;
+      if (!(xhi[k] >= 0.0)) continue;  // no residue terms
+      if (xhi[k] <= wp.core_max) {
+        has_core[c] = 1;
+      } else {
+        has_val[c] = 1;
+        lo = std::min(lo, xlo[k]);
+        hi = std::max(hi, xhi[k]);
+      }
+    }
+    if (has_val[c]) xv[c] = even_points((1.0 - wp.delta_lower) * lo, (1.0 + wp.delta_upper) * hi, NV);
+  }
+  // reference screening: W[c][m][j] for m < R_w, j < NC (core window) and
+  // NC + j (valence window of core c)
+  TaskList tl;
+  for (int c = 0; c < nc; ++c) {
+    const long long base = (long long)c * R_w * n_rr;
+    if (has_core[c])
+      for (int j = 0; j < NC; ++j) {
+        tl.z.push_back(make_double2(xc[j], args->eta));
+        tl.n.push_back(in.core[c]);
+        tl.m.push_back(-1);
+        tl.out_base.push_back(base + j);
+        tl.out_stride.push_back(n_rr);
+      }
+    if (has_val[c])
+      for (int j = 0; j < NV; ++j) {
+        tl.z.push_back(make_double2(xv[c][j], args->eta));
+        tl.n.push_back(in.core[c]);
+        tl.m.push_back(-1);
+        tl.out_base.push_back(base + NC + j);
+        tl.out_stride.push_back(n_rr);
+      }
+  }
+  DevBuf dWref(s);
+  dWref.alloc((size_t)nc * R_w * n_rr * sizeof(double2));
+  run_screening(rs, mx, args->precision, tl, R_w, dWref.as<double2>(), status, s, batch_bytes);
+
+  // pairs and their nodes: imaginary nodes, then the window's real points
+  std::vector<int4> pairs;
+  std::vector<long long> noff;
+  std::vector<double2> nz;
+  std::vector<int> pidx((size_t)nc * nb, -1);
+  for (int c = 0; c < nc; ++c)
+    for (int m = 0; m < nb; ++m) {
+      const size_t k = (size_t)c * nb + m;
+      if (!(xhi[k] >= 0.0)) continue;
+      const bool core = xhi[k] <= wp.core_max;
+      const std::vector<double> &xs = core ? xc : xv[c];
+      pidx[k] = (int)pairs.size();
+      pairs.push_back(make_int4(c, m, core ? 0 : NC, ni + (int)xs.size()));
+      noff.push_back((long long)nz.size());
+      for (int q = 0; q < ni; ++q) nz.push_back(make_double2(0.0, in.wi[q]));
+      for (double x : xs) nz.push_back(make_double2(x, args->eta));
+    }
+  std::vector<int> pot(T);
+  for (size_t t = 0; t < T; ++t) pot[t] = pidx[(size_t)task_core[t] * nb + tr.m[t]];
+  DevBuf dpairs(s), dnoff(s), dnz(s), dcoef(s), dpot(s), dzt(s), dst(s);
+  const int4 *d_pairs = upload(dpairs, pairs, s);
+  const long long *d_noff = upload(dnoff, noff, s);
+  const double2 *d_nz = upload(dnz, nz, s);
+  const int *d_pot = upload(dpot, pot, s);
+  const double2 *d_zt = upload(dzt, tr.z, s);
+  dcoef.alloc(nz.size() * sizeof(double2));
+  const std::vector<int> zero(1, 0);
+  int *d_st = upload(dst, zero, s);
+  launch_pade_fit(d_pairs, (int)pairs.size(), d_noff, d_nz, d_Wimag, nb, ni, dWref.as<double2>(),
+                  R_w, n_rr, dcoef.as<double2>(), d_st, s);
+  launch_pade_eval(d_zt, d_pot, d_pairs, d_noff, d_nz, dcoef.as<double2>(), (int)T, d_Wreal, s);
+  HIPCHECK(hipGetLastError());
+  int flag = 0;
+  HIPCHECK(hipMemcpyAsync(&flag, d_st, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  if (flag) fail(GWC_ERR_FACTORIZATION, "CD-WAC continued-fraction fit broke down (zero reciprocal difference)");
+}
+
 }  // namespace
 
 void validate_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
@@ -591,7 +728,13 @@ size_t predict_sigma_bytes(const ResidentSystem &rs, const gwc_sigma_args *args,
   const size_t t_real = args->mode == GWC_MODE_FULL ? (size_t)nc * (nr + 1) * rs.nb
                                                     : (size_t)nc * ((size_t)nr * per_point + rs.nb);
   const BatchPlan pi = plan_batch(rs, (size_t)ni * nc, rs.nb, batch_bytes);
-  const BatchPlan pr = plan_batch(rs, t_real, 1, batch_bytes);
+  BatchPlan pr = plan_batch(rs, t_real, 1, batch_bytes);
+  if (args->wac) {
+    const gwc_wac_params &w = *args->wac;
+    const BatchPlan pw = plan_batch(rs, (size_t)nc * (std::max(w.n_core_pts, 0) + std::max(w.n_val_pts, 0)),
+                                    rs.nb, batch_bytes);
+    if (pw.bytes > pr.bytes) pr = pw;
+  }
   const size_t fixed = (size_t)nc * rs.nb * ni * sizeof(double2) + t_real * (sizeof(double2) + sizeof(double)) +
                        (size_t)nc * (nr + 1) * 8 * sizeof(double) + (1 << 20);
   return std::max(pi.bytes, pr.bytes) + fixed;
@@ -639,7 +782,10 @@ void run_sigma(ResidentSystem &rs, const gwc_sigma_args *args, gwc_sigma_out *ou
   build_residue_tasks(rs, args, in, tr, ftask, cj_off, tdec);
   DevBuf dWr(s);
   dWr.alloc(std::max<size_t>(tr.size(), 1) * sizeof(double2));
-  run_screening(rs, mx, args->precision, tr, 1, dWr.as<double2>(), status, s, batch_bytes);
+  if (in.wac)
+    run_wac(rs, mx, args, in, tr, cj_off, dWi.as<double2>(), dWr.as<double2>(), status, s, batch_bytes);
+  else
+    run_screening(rs, mx, args->precision, tr, 1, dWr.as<double2>(), status, s, batch_bytes);
   for (int v : status)
     if (v) fail(GWC_ERR_FACTORIZATION, "exactly singular pivot in the LU of 1 - Pi(z)");
 

@@ -88,4 +88,15 @@ void launch_extract_spectrum(const double2 *Gw, int n_out, double *A_out, hipStr
 // (TFLOP/s), 3 HBM copy (GB/s, read + write).
 hipError_t probe_peak(int kind, hipStream_t s, double *value);
 
+// CD-WAC Pade fits (kernels_wac.hip): at most WAC_MAX_NODES reference points
+// per fitted pair (imaginary nodes plus one real window).
+constexpr int WAC_MAX_NODES = 1024;
+void launch_pade_fit(const int4 *pairs, int n_pairs, const long long *node_off,
+                     const double2 *node_z, const double2 *W_imag, int nb, int ni,
+                     const double2 *W_ref, int R_w, int n_rr, double2 *coef, int *status,
+                     hipStream_t stream);
+void launch_pade_eval(const double2 *z_task, const int *pair_of_task, const int4 *pairs,
+                      const long long *node_off, const double2 *node_z, const double2 *coef,
+                      int T, double2 *W_out, hipStream_t stream);
+
 }  // namespace gwc

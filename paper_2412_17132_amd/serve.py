@@ -8,7 +8,7 @@ import ctypes
 import numpy as np
 
 from . import _native as N
-from .api import _as_arg, _as_out, _stream_handle
+from .api import _as_arg, _as_out, _stream_handle, wac_arg
 
 
 class ResidentSystem:
@@ -31,7 +31,7 @@ class ResidentSystem:
         return cls(s.eps, s.occ, s.M_oo, s.M_ov)
 
     def sigma_core(self, core_idx, omega_imag, w_imag, omega_real, eta, vxc=None, mode="full",
-                   precision="fp64", stream=None, sym_group=None):
+                   precision="fp64", stream=None, sym_group=None, wac=None):
         """gwc_sigma_core_resident; outputs as NumPy arrays."""
         lib = N.load()
         keep: list = []
@@ -42,7 +42,8 @@ class ResidentSystem:
         args = N.GwcSigmaArgs(n_core, _as_arg(core_idx, "i4", keep), n_imag,
                               _as_arg(omega_imag, "f8", keep), _as_arg(w_imag, "f8", keep), n_real,
                               _as_arg(omega_real, "f8", keep), float(eta), _as_arg(vxc, "f8", keep),
-                              N.MODES[mode], N.PRECISIONS[precision], _as_arg(sym_group, "i4", keep))
+                              N.MODES[mode], N.PRECISIONS[precision], _as_arg(sym_group, "i4", keep),
+                              wac_arg(wac, keep))
         out = {
             "sigma_c": np.empty((n_core, n_real, 2)) if mode == "full" else None,
             "im_sigma_dec": np.empty((n_core, n_real)),

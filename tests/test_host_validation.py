@@ -110,3 +110,15 @@ def test_null_arguments_rejected(gwc):
     assert st == -1
     assert b"NULL" in lib.gwc_last_error()
     assert lib.gwc_spectral_cumulant(None, None, None, None) == -1
+
+
+def test_wac_argument_errors(gwc):
+    from oracle import wac as OW
+    s = _sys()
+    bad = [(dict(OW.paper_params(), n_core_pts=1), -2), (dict(OW.paper_params(), core_max=-1.0), -1),
+           (dict(OW.paper_params(), delta_lower=1.5), -1), (dict(OW.paper_params(), n_val_pts=2000), -2),
+           (dict(OW.paper_params(), delta_upper=float("nan")), -4)]
+    for p, status in bad:
+        with pytest.raises(gwc.GwcError) as ei:
+            _call(gwc, s, wac=p)
+        assert ei.value.status == status, (p, str(ei.value))
