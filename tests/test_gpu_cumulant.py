@@ -48,3 +48,42 @@ def test_cumulant_sum_rule_and_host_pointers():
     assert isinstance(A, np.ndarray)
     assert abs(np.sum(A) * dw - 1.0) < 1e-12
     assert 0.0 < z[0] < 1.0
+
+
+@pytest.mark.parametrize("structured", [False, True])
+def test_full_and_decoupled_spectra(structured):
+    """A(w) from the full Im Sigma^c (Eq. cd_sigma_imaginary: every residue) and
+    from the decoupled one (Eq. cd_sigma_imaginary_decoupled), end to end on the
+    GPU at c1, each against the oracle.  With core-localised coefficients the two
+    agree (the off-diagonal W_nm vanish); with i.i.d. coefficients the full one
+    carries extra correlation-satellite weight 1 - Z, the effect the decoupling
+    removes."""
+    from oracle import sigma as OS
+    from workloads import CONFIGS, system_from_config
+    dev = torch.device("cuda:0")
+    s = system_from_config(CONFIGS["c1"], structured=structured)
+    print(f"case full vs decoupled spectra structured={structured}", flush=True)
+    d = gwc.to_device(s, dev)
+    out = gwc.gwc_sigma_core(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],
+                             d["omega_imag"], d["w_imag"], d["omega_real"], d["eta"], mode="full")
+    ref = OS.sigma_core_system(s)
+    n = int(s.core_idx[0])
+    e_qp = float(out["e_qp"][0])
+    dw, n_t, n_out = 0.01 / EV_PER_HA, 2 ** 14, 3000
+    w0 = e_qp - 25 / EV_PER_HA
+    spectra = {}
+    for name, im, im_ref in (("full", out["sigma_c"][0, :, 1], ref["sigma_c"][0].imag),
+                             ("dec", out["im_sigma_dec"][0], ref["im_sigma_dec"][0])):
+        A, z = gwc.gwc_spectral_cumulant(d["omega_real"][0], im, float(s.eps[n]), e_qp, s.eta, n_t,
+                                         dw, n_out, w0)
+        torch.cuda.synchronize()
+        Ar, Zr, _ = OC.spectral_cumulant(s.omega_real[0], im_ref, float(s.eps[n]),
+                                         float(ref["e_qp"][0]), s.eta, n_t, dw, n_out, w0)
+        A = A.cpu().numpy()
+        assert np.max(np.abs(A - Ar)) <= TOL * np.max(Ar), name
+        spectra[name] = (A, float(z[0]))
+    dA = np.max(np.abs(spectra["full"][0] - spectra["dec"][0])) / np.max(spectra["dec"][0])
+    if structured:
+        assert dA < 1e-8
+    else:
+        assert 1.0 - spectra["full"][1] > 2.0 * (1.0 - spectra["dec"][1])
