@@ -400,12 +400,15 @@ lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, in
 }
 
 // ===========================================================================
-// S: row moves on the trailing columns and U12 = L11^-1 A12 (16 columns per
-// workgroup, 4 waves of 16 rows each).
+// S: row moves on columns [c_start, c_end) (16 per workgroup, 4 waves of 16
+// rows each); with u12, then U12 = L11^-1 A12 for the panel rows K0..K0+64,
+// after subtracting the previous 64-column block's contribution
+// A[K0.., kpre..kpre+64] A[kpre..kpre+64, ..] when kpre >= 0 (the second
+// panel of a 128-column step, whose rows the wide trailing update skips).
 __global__ void __launch_bounds__(256)
 lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0, int F,
-                   int nchunks, const int *__restrict__ moves_g,
-                   const double2 *__restrict__ linv_g) {
+                   int nchunks, int c_start, int c_end, int kpre, int u12,
+                   const int *__restrict__ moves_g, const double2 *__restrict__ linv_g) {
   __shared__ int mv[1 + 2 * MAX_MOVES];
   __shared__ double2 val[MAX_MOVES][SW + 1];
   int f, chunk;
@@ -413,8 +416,8 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int n = N + R;
-  const int kbo = min(NBO, N - K0), kend = K0 + kbo;
-  const int c0 = kend + chunk * SW, cw = min(SW, n - c0);
+  const int kbo = min(NBO, N - K0);
+  const int c0 = c_start + chunk * SW, cw = min(SW, c_end - c0);
   double2 *A = G + (long long)f * gs;
   const int *m = moves_g + (long long)f * (1 + 2 * MAX_MOVES);
   for (int i = tid; i < 1 + 2 * MAX_MOVES; i += 256) mv[i] = m[i];
@@ -429,12 +432,33 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
     const int i = idx / SW, j = idx - i * SW;
     if (j < cw) A[(long long)mv[1 + 2 * i] * ldg + c0 + j] = val[i][j];
   }
+  if (!u12) return;
   __syncthreads();
   for (int idx = tid; idx < NBO * SW; idx += 256) {
     const int t = idx / SW, j = idx - t * SW;
     val[t][j] = (t < kbo && j < cw) ? A[(long long)(K0 + t) * ldg + c0 + j] : make_double2(0.0, 0.0);
   }
   __syncthreads();
+  if (kpre >= 0) {
+    d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+    const int arow = K0 + 16 * wave + li;
+#pragma unroll 4
+    for (int kk = 0; kk < NBO; kk += 4) {
+      const int k = kpre + kk + lk;
+      const double2 a = (16 * wave + li < kbo) ? A[(long long)arow * ldg + k] : make_double2(0.0, 0.0);
+      const double2 b = (li < cw) ? A[(long long)k * ldg + c0 + li] : make_double2(0.0, 0.0);
+      yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, yr, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, yr, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, yi, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, yi, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = 16 * wave + 4 * r + lk;
+      val[t][li] = make_double2(val[t][li].x - yr[r], val[t][li].y - yi[r]);
+    }
+    __syncthreads();
+  }
   const double2 *Li = linv_g + (long long)f * NBO * NBO;
   d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
@@ -454,18 +478,19 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
 }
 
 // ===========================================================================
-// G: trailing update A22 -= L21 U12, one 64 x 64 tile per workgroup; the MFMA
-// operands come straight from memory (the panels of one matrix are shared in
-// its XCD's L2), so the K loop has no barriers.
+// G: trailing update A[rows, cols] -= A[rows, K] A[K, cols] over the K range
+// [kstart, kstart + klen) (64, or 128 for a two-panel step), one 64 x 64 tile
+// per workgroup on an mt_r x mt_c grid from (row0, col0); the MFMA operands
+// come straight from memory (the panels of one matrix are shared in its XCD's
+// L2), so the K loop has no barriers.
 __global__ void __launch_bounds__(256, 4)
-lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0, int F,
-                   int mt) {
+lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int F, int row0,
+                   int col0, int mt_r, int mt_c, int kstart, int klen) {
   int f, tile;
-  if (!xcd_map(blockIdx.x, mt * mt, F, f, tile)) return;
+  if (!xcd_map(blockIdx.x, mt_r * mt_c, F, f, tile)) return;
   const int n = N + R;
-  const int kbo = min(NBO, N - K0), kend = K0 + kbo;
-  const int ti = tile / mt, tj = tile - ti * mt;
-  const int ra = kend + ti * 64, ca = kend + tj * 64;
+  const int ti = tile / mt_c, tj = tile - ti * mt_c;
+  const int ra = row0 + ti * 64, ca = col0 + tj * 64;
   if (ra >= N && ca >= N && (ra + 64 <= ca || ca + 64 <= ra)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -488,18 +513,18 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
       }
     }
 #pragma unroll 4
-  for (int kk = 0; kk < kbo; kk += 4) {
+  for (int kk = 0; kk < klen; kk += 4) {
     const int k = kk + lk;
     double2 lv[2], uv[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int row = ra + wr + 16 * a + li;
-      lv[a] = (row < n && k < kbo) ? A[(long long)row * ldg + K0 + k] : make_double2(0.0, 0.0);
+      lv[a] = (row < n && k < klen) ? A[(long long)row * ldg + kstart + k] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int col = ca + wc + 16 * b + li;
-      uv[b] = (k < kbo && col < n) ? A[(long long)(K0 + k) * ldg + col] : make_double2(0.0, 0.0);
+      uv[b] = (k < klen && col < n) ? A[(long long)(kstart + k) * ldg + col] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -558,6 +583,48 @@ static void launch_panel(int F, double2 *G, long long gs, int ldg, int N, int R,
   lu_panel_kernel<RPT, W><<<F, PT, 0, stream>>>(G, gs, ldg, N, R, K0, piv, moves, linv, status);
 }
 
+namespace {
+
+struct LuLaunch {
+  double2 *G;
+  long long gs;
+  int ldg, N, R, F, fgroups;
+  int *piv, *moves, *status;
+  double2 *linv;
+  hipStream_t s;
+
+  void panel(int K0) const {
+    const int rpt = (N + R + PT - 1) / PT;
+    // register block v[RPT][W] kept at <= 128 VGPRs
+    if (rpt <= 1) launch_panel<1, 8>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 2) launch_panel<2, 8>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 3) launch_panel<3, 8>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 4) launch_panel<4, 8>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 6) launch_panel<6, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 8) launch_panel<8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 12) launch_panel<12, 2>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 16) launch_panel<16, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else launch_panel<24, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+  }
+  // row moves of the panel at K0 on columns [c0, c1); with u12 also its U rows
+  void swap_u12(int K0, int c0, int c1, int kpre, int u12) const {
+    const int nch = (c1 - c0 + SW - 1) / SW;
+    if (nch < 1) return;
+    lu_swap_u12_kernel<<<NXCD * fgroups * nch, 256, 0, s>>>(G, gs, ldg, N, R, K0, F, nch, c0, c1, kpre,
+                                                             u12, moves, linv);
+  }
+  // rows [r0, n) x columns [c0, c1) -= A[.., K range] A[K range, ..]
+  void trailing(int r0, int c0, int c1, int kstart, int klen) const {
+    const int n = N + R;
+    const int mt_r = (n - r0 + 63) / 64, mt_c = (c1 - c0 + 63) / 64;
+    if (mt_r < 1 || mt_c < 1) return;
+    lu_trailing_kernel<<<NXCD * fgroups * mt_r * mt_c, 256, 0, s>>>(G, gs, ldg, N, R, F, r0, c0, mt_r,
+                                                                     mt_c, kstart, klen);
+  }
+};
+
+}  // namespace
+
 void launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
                         const double *bb, const long long *out_base, const int *out_stride,
                         double2 *W_out, int *status, void *scratch, hipStream_t stream) {
@@ -567,27 +634,28 @@ void launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, i
   double2 *linv = reinterpret_cast<double2 *>(
       (reinterpret_cast<uintptr_t>(moves + (size_t)F * (1 + 2 * MAX_MOVES)) + 255) & ~uintptr_t(255));
   zero_int_kernel<<<(F + 255) / 256, 256, 0, stream>>>(status, F);
-  const int rpt = (n + PT - 1) / PT;
-  const int fgroups = (F + NXCD - 1) / NXCD;
-  for (int K0 = 0; K0 < N; K0 += NBO) {
-    const int kend = min(K0 + NBO, N);
-    // register block v[RPT][W] kept at <= 128 VGPRs
-    if (rpt <= 1) launch_panel<1, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    else if (rpt <= 2) launch_panel<2, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    else if (rpt <= 3) launch_panel<3, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    else if (rpt <= 4) launch_panel<4, 8>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    else if (rpt <= 6) launch_panel<6, 4>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    else if (rpt <= 8) launch_panel<8, 4>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    else if (rpt <= 12) launch_panel<12, 2>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    else if (rpt <= 16) launch_panel<16, 1>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    else launch_panel<24, 1>(F, G, g_stride, ldg, N, R, K0, piv, moves, linv, status, stream);
-    const int rem = n - kend;  // >= R >= 1
-    const int nch = (rem + SW - 1) / SW;
-    lu_swap_u12_kernel<<<NXCD * fgroups * nch, 256, 0, stream>>>(G, g_stride, ldg, N, R, K0, F,
-                                                                   nch, moves, linv);
-    const int mt = (rem + 63) / 64;
-    lu_trailing_kernel<<<NXCD * fgroups * mt * mt, 256, 0, stream>>>(G, g_stride, ldg, N, R, K0,
-                                                                      F, mt);
+  const LuLaunch L{G, g_stride, ldg, N, R, F, (F + NXCD - 1) / NXCD, piv, moves, status, linv, stream};
+  int K0 = 0;
+  while (K0 < N) {
+    if (N - K0 >= 2 * NBO) {
+      // two 64-column panels a, b, then one trailing update with K = 128:
+      // the A22 block streams through memory once per 128 columns
+      const int a = K0, b = K0 + NBO, e = K0 + 2 * NBO;
+      L.panel(a);
+      L.swap_u12(a, b, n, -1, 1);           // a's moves and U rows on every column right of it
+      L.trailing(b, b, b + NBO, a, NBO);    // a's update of panel b only
+      L.panel(b);
+      L.swap_u12(b, a, b, -1, 0);           // b's moves on a's L columns
+      L.swap_u12(b, e, n, a, 1);            // b's moves, a's update of rows b..e, b's U rows
+      L.trailing(e, e, n, a, 2 * NBO);      // rows, columns >= e with K = [a, e)
+      K0 = e;
+    } else {
+      const int kend = min(K0 + NBO, N);
+      L.panel(K0);
+      L.swap_u12(K0, kend, n, -1, 1);
+      L.trailing(kend, kend, n, K0, kend - K0);
+      K0 = kend;
+    }
   }
   lu_finish_kernel<<<F, 64, 0, stream>>>(G, g_stride, ldg, N, R, bb, out_base, out_stride, W_out);
 }
