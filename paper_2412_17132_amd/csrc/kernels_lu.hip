@@ -81,15 +81,12 @@ struct PanelShared {
   double2 prow[WMAX];
   double2 xbuf[WMAX];
   double2 lbb[WMAX][WMAX + 1];
-  union {
+  int pslot[NBO];
+  struct {
     struct {
       double2 stage[2 * WMAX][NBO];  // moved rows of the panel columns outside the block
       double2 U[WMAX][NBO];          // U rows of the block on the columns to its right
     } blk;
-    struct {
-      double2 L11[NBO][NBO + 1];
-      double2 X[NBO][NBO + 1];
-    } inv;
   } u;
 };
 
@@ -104,8 +101,8 @@ struct PanelShared {
 //      lower diagonal block (one thread per column, in registers);
 //   4. every thread applies the rank-W update to its own rows of those
 //      columns, with the block's L values still in its registers.
-template <int RPT, int W>
-__global__ void __launch_bounds__(PT, 1)
+template <int RPT, int W, int WPE>
+__global__ void __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(WPE)))
 lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0,
                 int *__restrict__ piv_g, int *__restrict__ moves_g, double2 *__restrict__ linv_g,
                 int *__restrict__ status) {
@@ -341,29 +338,31 @@ lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, in
   }
 
   if (tid < kbo) piv_g[(long long)f * NBO + tid] = sh.piv[tid];
-  // net row moves of the step: rows K0..kend plus the rows they swapped with
+  // net row moves of the step: slot t < kbo holds row K0 + t, slot kbo + t the
+  // pivot row piv[t] when it lies below the panel and t is its first use
+  if (tid < kbo) {
+    const int p = sh.piv[tid];
+    int first = tid;
+    if (p >= kend)
+      for (int u = 0; u < tid; ++u)
+        if (sh.piv[u] == p) { first = u; break; }
+    sh.pslot[tid] = p < kend ? p - K0 : kbo + first;
+    sh.mrow[tid] = K0 + tid;
+    sh.mcont[tid] = K0 + tid;
+    sh.mrow[kbo + tid] = p;
+    sh.mcont[kbo + tid] = p;
+  }
+  __syncthreads();
   if (tid == 0) {
-    int cnt = kbo;
-    for (int t = 0; t < kbo; ++t) { sh.mrow[t] = K0 + t; sh.mcont[t] = K0 + t; }
     for (int t = 0; t < kbo; ++t) {
-      const int p = sh.piv[t];
-      const int a = t;
-      int b;
-      if (p < kend) {
-        b = p - K0;
-      } else {
-        b = -1;
-        for (int i = kbo; i < cnt; ++i)
-          if (sh.mrow[i] == p) { b = i; break; }
-        if (b < 0) { b = cnt; sh.mrow[cnt] = p; sh.mcont[cnt] = p; ++cnt; }
-      }
-      const int tmp = sh.mcont[a];
-      sh.mcont[a] = sh.mcont[b];
+      const int b = sh.pslot[t];
+      const int tmp = sh.mcont[t];
+      sh.mcont[t] = sh.mcont[b];
       sh.mcont[b] = tmp;
     }
     int m = 0;
     int *mv = moves_g + (long long)f * (1 + 2 * MAX_MOVES);
-    for (int i = 0; i < cnt; ++i)
+    for (int i = 0; i < 2 * kbo; ++i)
       if (sh.mcont[i] != sh.mrow[i]) {
         mv[1 + 2 * m] = sh.mrow[i];
         mv[2 + 2 * m] = sh.mcont[i];
@@ -372,30 +371,41 @@ lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, in
     mv[0] = m;
     if (sh.flags) status[f] = 1;
   }
-  __syncthreads();
-  // L11^-1 (unit lower): column j = tid by forward substitution in LDS
-  for (int idx = tid; idx < NBO * NBO; idx += PT) {
-    const int i = idx / NBO, t = idx - i * NBO;
-    sh.u.inv.L11[i][t] = (i < kbo && t < i) ? A[(long long)(K0 + i) * ldg + K0 + t] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  if (tid < NBO) {
-    const int j = tid;
-    for (int i = 0; i < NBO; ++i) {
-      double2 x = make_double2(i == j ? 1.0 : 0.0, 0.0);
-      if (i > j && i < kbo) {
-        for (int t = j; t < i; ++t) x = csub(x, cmul(sh.u.inv.L11[i][t], sh.u.inv.X[t][j]));
-      } else if (i >= kbo) {
-        x = make_double2(0.0, 0.0);
-      }
-      sh.u.inv.X[i][j] = x;
-    }
-  }
-  __syncthreads();
-  double2 *Li = linv_g + (long long)f * NBO * NBO;
-  for (int idx = tid; idx < NBO * NBO; idx += PT) {
+}
+
+// L11^-1 of the step's panel (unit lower, 64 x 64), one workgroup per matrix,
+// in place in LDS, right-looking: X starts as L11 (identity on the diagonal);
+// at step t every row i > t takes X[i][j] -= L[i][t] X[t][j] for j < t and
+// X[i][t] = -L[i][t] (row t of X is final by then).  Thread tid owns row
+// tid / 4 and the columns j = tid % 4 (mod 4); L[i][t] is read before the
+// barrier that precedes its overwrite.
+__global__ void __launch_bounds__(256)
+lu_linv_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, int K0,
+               double2 *__restrict__ linv_g) {
+  __shared__ double2 X[NBO][NBO + 1];
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const double2 *A = G + (long long)f * gs;
+  const int kbo = min(NBO, N - K0);
+  for (int idx = tid; idx < NBO * NBO; idx += 256) {
     const int i = idx / NBO, j = idx - i * NBO;
-    Li[idx] = (i < kbo && j < kbo) ? sh.u.inv.X[i][j] : make_double2(0.0, 0.0);
+    X[i][j] = (i < kbo && j < i) ? A[(long long)(K0 + i) * ldg + K0 + j]
+                                 : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const int i = tid >> 2, j0 = tid & 3;
+  for (int t = 0; t < NBO - 1; ++t) {
+    const double2 l = X[i][t];
+    __syncthreads();
+    if (i > t) {
+      for (int j = j0; j < t; j += 4) X[i][j] = csub(X[i][j], cmul(l, X[t][j]));
+      if ((t & 3) == j0) X[i][t] = make_double2(-l.x, -l.y);
+    }
+    __syncthreads();
+  }
+  double2 *Li = linv_g + (long long)f * NBO * NBO;
+  for (int idx = tid; idx < NBO * NBO; idx += 256) {
+    const int r = idx / NBO, c = idx - r * NBO;
+    Li[idx] = (r < kbo && c < kbo) ? X[r][c] : make_double2(0.0, 0.0);
   }
 }
 
@@ -577,10 +587,12 @@ size_t lu_scratch_bytes(int F) {
 
 int lu_max_order() { return 24 * PT; }
 
-template <int RPT, int W>
+// WPE: waves per SIMD the register allocation must allow (4: two panel
+// workgroups per CU, where that costs at most a small spill)
+template <int RPT, int W, int WPE>
 static void launch_panel(int F, double2 *G, long long gs, int ldg, int N, int R, int K0, int *piv,
                          int *moves, double2 *linv, int *status, hipStream_t stream) {
-  lu_panel_kernel<RPT, W><<<F, PT, 0, stream>>>(G, gs, ldg, N, R, K0, piv, moves, linv, status);
+  lu_panel_kernel<RPT, W, WPE><<<F, PT, 0, stream>>>(G, gs, ldg, N, R, K0, piv, moves, linv, status);
 }
 
 namespace {
@@ -596,15 +608,16 @@ struct LuLaunch {
   void panel(int K0) const {
     const int rpt = (N + R + PT - 1) / PT;
     // register block v[RPT][W] kept at <= 128 VGPRs
-    if (rpt <= 1) launch_panel<1, 8>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 2) launch_panel<2, 8>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 3) launch_panel<3, 8>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 4) launch_panel<4, 8>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 6) launch_panel<6, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 8) launch_panel<8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 12) launch_panel<12, 2>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 16) launch_panel<16, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else launch_panel<24, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    if (rpt <= 1) launch_panel<1, 8, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 2) launch_panel<2, 8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 3) launch_panel<3, 8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 4) launch_panel<4, 8, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 6) launch_panel<6, 4, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 8) launch_panel<8, 4, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 12) launch_panel<12, 2, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else if (rpt <= 16) launch_panel<16, 1, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    else launch_panel<24, 1, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    lu_linv_kernel<<<F, 256, 0, s>>>(G, gs, ldg, N, K0, linv);
   }
   // row moves of the panel at K0 on columns [c0, c1); with u12 also its U rows
   void swap_u12(int K0, int c0, int c1, int kpre, int u12) const {
