@@ -465,8 +465,8 @@ void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, c
     launch_border(rs.d_Moo.as<double>(), rs.d_Mov.as<double>(), N, rs.no, rs.nv, n_d + t0, m_d + t0,
                   Fb, R, dG.as<double2>(), (long long)mat_elems, ldg, dbb.as<double>(), s);
     hipEvent_t eb = timing ? timing_mark(s) : nullptr;
-    launch_lu_bordered(dG.as<double2>(), (long long)mat_elems, ldg, N, R, Fb, dbb.as<double>(),
-                       ob_d + t0, os_d + t0, W_out, dst.as<int>() + t0, dscr.p, s);
+    HIPCHECK(launch_lu_bordered(dG.as<double2>(), (long long)mat_elems, ldg, N, R, Fb, dbb.as<double>(),
+                                ob_d + t0, os_d + t0, W_out, dst.as<int>() + t0, dscr.p, s));
     if (timing) {
       const double fl = Fb * ((8.0 / 3.0) * N * (double)N * N + 8.0 * (double)N * N * R);
       pending.push_back({1, eb, timing_mark(s), fl});

@@ -55,9 +55,10 @@ void launch_border(const double *M_oo, const double *M_ov, int n_aux, int n_occ,
 // up to lu_max_order() (= N + R) are supported.
 size_t lu_scratch_bytes(int F);
 int lu_max_order();
-void launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
-                        const double *bb, const long long *out_base, const int *out_stride,
-                        double2 *W_out, int *status, void *scratch, hipStream_t stream);
+// Issues the factorisation on `stream`; returns the first HIP launch error.
+hipError_t launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
+                              const double *bb, const long long *out_base, const int *out_stride,
+                              double2 *W_out, int *status, void *scratch, hipStream_t stream);
 
 void launch_sigma_x(const double *M_oo, int n_aux, int n_occ, const int *core_idx, int n_core,
                     double *sigma_x, hipStream_t stream);

@@ -15,18 +15,20 @@
 // Only the diagonal of the R x R border block is needed, so border-border
 // tiles away from the diagonal are skipped.
 //
-// Batched right-looking LU in steps of NBO = 64 columns, three launches per
-// step over all matrices of the batch:
+// Batched right-looking LU over all matrices of a batch, in 64-column panels:
 //   P  one workgroup per matrix: the 64-wide panel (rows K0..n) is factored in
 //      register-resident column blocks of width W (partial pivoting, rank-1
 //      updates in registers, pivot row broadcast through LDS), with the block
 //      updates inside the panel on MFMA; then the permutation of the step as a
-//      list of row moves, and L11^-1 (64 x 64 unit lower) for the next launch;
-//   S  one workgroup per (matrix, 16 trailing columns): applies the row moves
-//      and forms U12 = L11^-1 A12 on MFMA;
-//   G  one workgroup per (matrix, 64 x 64 trailing tile): A22 -= L21 U12 with
-//      K = 64 on MFMA (the complex product as four real products), tiles of a
-//      matrix kept on one XCD so its L21 / U12 panels stay in that L2.
+//      list of row moves;
+//   L  L11^-1 (64 x 64 unit lower) of the panel, for the next launch;
+//   S  one workgroup per (matrix, 16 columns): applies the row moves and forms
+//      U12 = L11^-1 A12 on MFMA;
+//   G  one workgroup per (matrix, 64 x 64 tile): A22 -= L21 U12 on MFMA (the
+//      complex product as four real products), tiles of a matrix kept on one
+//      XCD so its L21 / U12 panels stay in that L2.
+// Two panels share one trailing update with K = 128 while at least 128 pivot
+// columns remain.
 #include "gwc_internal.h"
 
 namespace gwc {
@@ -490,12 +492,13 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
 // ===========================================================================
 // G: trailing update A[rows, cols] -= A[rows, K] A[K, cols] over the K range
 // [kstart, kstart + klen) (64, or 128 for a two-panel step), one 64 x 64 tile
-// per workgroup on an mt_r x mt_c grid from (row0, col0); the MFMA operands
+// per workgroup on an mt_r x mt_c grid from (row0, col0), columns below col_end
+// only (a range may end inside a tile); the MFMA operands
 // come straight from memory (the panels of one matrix are shared in its XCD's
 // L2), so the K loop has no barriers.
 __global__ void __launch_bounds__(256, 4)
 lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int F, int row0,
-                   int col0, int mt_r, int mt_c, int kstart, int klen) {
+                   int col0, int col_end, int mt_r, int mt_c, int kstart, int klen) {
   int f, tile;
   if (!xcd_map(blockIdx.x, mt_r * mt_c, F, f, tile)) return;
   const int n = N + R;
@@ -517,7 +520,7 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
       for (int r = 0; r < 4; ++r) {
         const int row = ra + wr + 16 * a + 4 * r + lk;
         double2 v = make_double2(0.0, 0.0);
-        if (row < n && col < n) v = A[(long long)row * ldg + col];
+        if (row < n && col < col_end) v = A[(long long)row * ldg + col];
         cre[a][b][r] = v.x;
         cim[a][b][r] = v.y;
       }
@@ -534,7 +537,7 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int col = ca + wc + 16 * b + li;
-      uv[b] = (k < klen && col < n) ? A[(long long)(kstart + k) * ldg + col] : make_double2(0.0, 0.0);
+      uv[b] = (k < klen && col < col_end) ? A[(long long)(kstart + k) * ldg + col] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -556,7 +559,7 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = ra + wr + 16 * a + 4 * r + lk;
-        if (row < n && col < n) A[(long long)row * ldg + col] = make_double2(cre[a][b][r], cim[a][b][r]);
+        if (row < n && col < col_end) A[(long long)row * ldg + col] = make_double2(cre[a][b][r], cim[a][b][r]);
       }
     }
 }
@@ -631,16 +634,16 @@ struct LuLaunch {
     const int n = N + R;
     const int mt_r = (n - r0 + 63) / 64, mt_c = (c1 - c0 + 63) / 64;
     if (mt_r < 1 || mt_c < 1) return;
-    lu_trailing_kernel<<<NXCD * fgroups * mt_r * mt_c, 256, 0, s>>>(G, gs, ldg, N, R, F, r0, c0, mt_r,
-                                                                     mt_c, kstart, klen);
+    lu_trailing_kernel<<<NXCD * fgroups * mt_r * mt_c, 256, 0, s>>>(G, gs, ldg, N, R, F, r0, c0, c1,
+                                                                     mt_r, mt_c, kstart, klen);
   }
 };
 
 }  // namespace
 
-void launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
-                        const double *bb, const long long *out_base, const int *out_stride,
-                        double2 *W_out, int *status, void *scratch, hipStream_t stream) {
+hipError_t launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
+                              const double *bb, const long long *out_base, const int *out_stride,
+                              double2 *W_out, int *status, void *scratch, hipStream_t stream) {
   const int n = N + R;
   int *piv = static_cast<int *>(scratch);
   int *moves = piv + (size_t)F * NBO;
@@ -671,6 +674,7 @@ void launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, int R, i
     }
   }
   lu_finish_kernel<<<F, 64, 0, stream>>>(G, g_stride, ldg, N, R, bb, out_base, out_stride, W_out);
+  return hipGetLastError();
 }
 
 }  // namespace gwc

@@ -27,7 +27,8 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 
 constexpr int MX_TR = 64;    // tile rows
-constexpr int MX_TC = 256;   // tile columns
+constexpr int MX_TC = MX_TILE_COLS;  // tile columns
+constexpr int MX_NB = MX_TC / 32;      // 16-column blocks per wave (a wave covers MX_TC / 2)
 constexpr int MX_KC = 32;    // K per LDS stage
 constexpr int MX_THREADS = 256;
 
@@ -129,8 +130,8 @@ struct Mfma<_Float16> {
   }
 };
 
-// Grid: (n_tiles, F).  Wave w: rows 32*(w/2) .. +32, columns 128*(w%2) .. +128,
-// i.e. 2 x 8 blocks of 16 x 16, Re and Im accumulators (FP32).
+// Grid: (n_tiles, F).  Wave w: rows 32*(w/2) .. +32, columns (MX_TC/2)*(w%2)
+// .. +MX_TC/2, i.e. 2 x MX_NB blocks of 16 x 16, Re and Im accumulators (FP32).
 // MFMA layout (16x16x32): lane l supplies A[l%16][8(l/16)+e], B[8(l/16)+e][l%16];
 // output element r of lane l is D[4(l/16)+r][l%16].
 template <class T>
@@ -152,14 +153,14 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const unsigned short *__rest
   const int2 tb = tiles[blockIdx.x];
   const int P0 = tb.x * MX_TR, Q0 = tb.y * MX_TC;
   const int f = blockIdx.y;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 128;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * (MX_TC / 2);
   const float gsc = tscale ? tscale[f] : 1.0f;
 
-  f4 accr[2][8], acci[2][8];
+  f4 accr[2][MX_NB], acci[2][MX_NB];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < MX_NB; ++b) {
       accr[a][b] = f4{0.f, 0.f, 0.f, 0.f};
       acci[a][b] = f4{0.f, 0.f, 0.f, 0.f};
     }
@@ -176,10 +177,10 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const unsigned short *__rest
       float *dst = As + row * LA + kq;
       dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
     }
-    // B: 256 rows x 32 halves, hi and lo (16 halves = 32 B per thread each)
+    // B: MX_TC rows x 32 halves, hi and lo (8 halves = 16 B per thread and pass)
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int idx = it * MX_THREADS + tid;       // 0..1023
+    for (int it = 0; it < MX_TC / 64; ++it) {
+      const int idx = it * MX_THREADS + tid;       // 0 .. 4 MX_TC - 1
       const int row = idx >> 2, kq = (idx & 3) * 8;
       const long long off = (long long)(Q0 + row) * ldl + kc + kq;
       const uint4 vh = *reinterpret_cast<const uint4 *>(Bhi + off);
@@ -212,7 +213,7 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const unsigned short *__rest
       }
     }
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < MX_NB; ++b) {
       const int col = wc + 16 * b + li;
       const us8 bh = *reinterpret_cast<const us8 *>(Bh + col * LB + 8 * lq);
       const us8 bl = *reinterpret_cast<const us8 *>(Bl + col * LB + 8 * lq);
@@ -235,7 +236,7 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const unsigned short *__rest
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
+    for (int b = 0; b < MX_NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = P0 + wr + 16 * a + 4 * lq + r;
