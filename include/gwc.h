@@ -59,7 +59,9 @@ enum gwc_precision {
   GWC_PREC_FP64 = 0,   /* everything in float64 */
   GWC_PREC_BF16X3 = 1, /* Pi build as hi*hi + hi*lo + lo*hi bf16 products, fp32 accumulation */
   GWC_PREC_FP16X3 = 2, /* same with fp16 and power-of-two column and frequency scaling */
-  GWC_PREC_FP8 = 3     /* reserved: returns GWC_ERR_UNSUPPORTED */
+  GWC_PREC_FP8 = 3     /* fp8 e4m3 hi*hi + hi*lo + lo*hi, fp32 accumulation, power-of-two column
+                        * and frequency scaling aimed below the e4m3 limit (448); ~2^-7
+                        * relative per product, so ~1e-3 on Sigma^c: a throughput option */
 };
 
 /* A closed-shell system in the RI representation.

@@ -280,7 +280,7 @@ struct ResidentSystem {
   PersistBuf d_eps, d_Moo, d_Mov, d_L, d_tiles;
   int n_tiles = 0;
   std::mutex mixed_mutex;
-  MixedOperands mixed[3];  // by precision (1, 2)
+  MixedOperands mixed[4];  // by precision (1, 2, 3)
 };
 
 int resident_n_occ(const ResidentSystem &rs) { return rs.no; }
@@ -369,8 +369,7 @@ const MixedOperands &mixed_operands(ResidentSystem &rs, int prec, hipStream_t s)
   m.ics.alloc(rs.ldl * sizeof(float));
   m.acol.alloc(rs.ldl * sizeof(float));
   launch_mixed_prep(prec, rs.d_L.as<double>(), rs.n_aux_pad, rows_pad, rs.ldl, m.Lf.as<float>(),
-                    m.Bh.as<unsigned short>(), m.Bl.as<unsigned short>(), m.cs.as<float>(),
-                    m.ics.as<float>(), m.acol.as<float>(), s);
+                    m.Bh.p, m.Bl.p, m.cs.as<float>(), m.ics.as<float>(), m.acol.as<float>(), s);
   std::vector<int2> mt;
   const int nr_t = (rs.N + MX_TILE_ROWS - 1) / MX_TILE_ROWS;
   const int nc_t = (rs.N + MX_TILE_COLS - 1) / MX_TILE_COLS;
@@ -449,10 +448,9 @@ void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, c
                           rs.d_tiles.as<int2>(), rs.n_tiles, dG.as<double2>(), (long long)mat_elems,
                           ldg, s);
     } else {
-      launch_pi_build_mixed(precision, mx->Lf.as<float>(), mx->Bh.as<unsigned short>(),
-                            mx->Bl.as<unsigned short>(), rs.ldl, N, dchr.as<double>(),
-                            dchi.as<double>(),
-                            precision == GWC_PREC_FP16X3 ? mx->ics.as<float>() : nullptr,
+      launch_pi_build_mixed(precision, mx->Lf.as<float>(), mx->Bh.p, mx->Bl.p, rs.ldl, N,
+                            dchr.as<double>(), dchi.as<double>(),
+                            precision != GWC_PREC_BF16X3 ? mx->ics.as<float>() : nullptr,
                             mx->acol.as<float>(), dts.as<float>(), Fb, mx->tiles.as<int2>(),
                             mx->n_tiles, dG.as<double2>(), (long long)mat_elems, ldg, s);
     }
@@ -499,8 +497,6 @@ SigmaInputs check_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
     fail(GWC_ERR_INVALID_ARG, "unknown mode %d", args->mode);
   if (args->precision < GWC_PREC_FP64 || args->precision > GWC_PREC_FP8)
     fail(GWC_ERR_INVALID_ARG, "unknown precision %d", args->precision);
-  if (args->precision == GWC_PREC_FP8)
-    fail(GWC_ERR_UNSUPPORTED, "precision %d (FP8) is not implemented in this build", args->precision);
   if (out && args->mode == GWC_MODE_FULL && !out->sigma_c)
     fail(GWC_ERR_INVALID_ARG, "sigma_c is required in FULL mode");
   SigmaInputs in;

@@ -40,14 +40,16 @@ void launch_pi_build_f64(const double *Lp, int ldl, int n_aux, const double *chi
 // padded to a multiple of MX_TILE_COLS.
 constexpr int MX_TILE_ROWS = 64;
 constexpr int MX_TILE_COLS = 256;
+// prec 1 BF16X3, 2 FP16X3, 3 FP8X3; Bhi / Blo hold 16-bit (1, 2) or 8-bit (3)
+// elements.
 void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, float *Lf,
-                       unsigned short *Bhi, unsigned short *Blo, float *colscale,
-                       float *inv_colscale, float *acol, hipStream_t stream);
-void launch_pi_build_mixed(int prec, const float *Lf, const unsigned short *Bhi,
-                           const unsigned short *Blo, int ldl, int n_aux, const double *chi_re,
-                           const double *chi_im, const float *inv_colscale, const float *acol,
-                           float *tscale, int F, const int2 *tiles, int n_tiles, double2 *G,
-                           long long g_stride, int ldg, hipStream_t stream);
+                       void *Bhi, void *Blo, float *colscale, float *inv_colscale, float *acol,
+                       hipStream_t stream);
+void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const void *Blo, int ldl,
+                           int n_aux, const double *chi_re, const double *chi_im,
+                           const float *inv_colscale, const float *acol, float *tscale, int F,
+                           const int2 *tiles, int n_tiles, double2 *G, long long g_stride, int ldg,
+                           hipStream_t stream);
 void launch_border(const double *M_oo, const double *M_ov, int n_aux, int n_occ, int n_virt,
                    const int *task_n, const int *task_m, int F, int R, double2 *G,
                    long long g_stride, int ldg, double *bb, hipStream_t stream);

@@ -13,6 +13,8 @@
 //           are scaled by 2^e_k (undone in A), and each frequency's A operand
 //           by 2^g_f (undone on the FP32 result), keeping hi and lo parts in the
 //           fp16 normal range -> ~2^-22 relative per product
+//   FP8X3:  fp8 e4m3 (4-bit significand, largest 448) with the same scaling
+//           aimed one binade higher -> ~2^-7 relative per product
 //
 // Tile: one 64 x 256 block of Pi per workgroup and frequency (4 waves of
 // 32 x 128, v_mfma_f32_16x16x32_{bf16,f16}), upper-triangle blocks only, the
@@ -25,6 +27,10 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+typedef unsigned char uc8 __attribute__((ext_vector_type(8)));
+
+// fp8 e4m3 (the MFMA's fp8 operand format on this target)
+struct e4m3 {};
 
 constexpr int MX_TR = 64;    // tile rows
 constexpr int MX_TC = MX_TILE_COLS;  // tile columns
@@ -44,16 +50,58 @@ __device__ __forceinline__ void split16(float x, unsigned short &hi, unsigned sh
   lo = to_bits((T)r);
 }
 
+// Per-form operand traits: storage element E, MFMA operand V (8 elements of
+// one lane), the hi/lo split, the product, and the binade the scaling aims the
+// largest |value| at (0: no scaling).
+template <class T>
+struct Mix;
+template <>
+struct Mix<__bf16> {
+  using E = unsigned short;
+  using V = us8;
+  static constexpr int TARGET = 0;
+  static __device__ __forceinline__ void split(float x, E &h, E &l) { split16<__bf16>(x, h, l); }
+  static __device__ __forceinline__ f4 mfma(V a, V b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+  }
+};
+template <>
+struct Mix<_Float16> {
+  using E = unsigned short;
+  using V = us8;
+  static constexpr int TARGET = 7;  // max |x| in [2^6, 2^7)
+  static __device__ __forceinline__ void split(float x, E &h, E &l) { split16<_Float16>(x, h, l); }
+  static __device__ __forceinline__ f4 mfma(V a, V b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+  }
+};
+template <>
+struct Mix<e4m3> {
+  using E = unsigned char;
+  using V = uc8;
+  static constexpr int TARGET = 8;  // max |x| in [2^7, 2^8), below the e4m3 limit 448
+  static __device__ __forceinline__ void split(float x, E &h, E &l) {
+    const int hp = __builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false);  // round to nearest even
+    const float r = x - __builtin_amdgcn_cvt_f32_fp8(hp, 0);
+    const int lp = __builtin_amdgcn_cvt_pk_fp8_f32(r, 0.0f, 0, false);
+    h = (E)(hp & 0xff);
+    l = (E)(lp & 0xff);
+  }
+  static __device__ __forceinline__ f4 mfma(V a, V b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0, 0, 0);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Per-call preparation: FP32 copy of L (A source) and the split B operand,
-// all [rows_pad][ldl] with rows beyond n_aux_pad zero.  For FP16 each column k
-// carries the scale 2^e_k (max_P |L_Pk| 2^e_k in [2^6, 2^7)); A is formed with
-// 2^-e_k.  For BF16 colscale is NULL (no scaling).
+// all [rows_pad][ldl] with rows beyond n_aux_pad zero.  For FP16 and FP8 each
+// column k carries the scale 2^e_k (max_P |L_Pk| 2^e_k in the form's target
+// binade); A is formed with 2^-e_k.  For BF16 colscale is NULL (no scaling).
 template <class T>
 __global__ void mixed_prep_kernel(const double *__restrict__ Lp, int n_aux_pad, int rows_pad,
                                   int ldl, const float *__restrict__ colscale,
-                                  float *__restrict__ Lf, unsigned short *__restrict__ Bhi,
-                                  unsigned short *__restrict__ Blo) {
+                                  float *__restrict__ Lf, typename Mix<T>::E *__restrict__ Bhi,
+                                  typename Mix<T>::E *__restrict__ Blo) {
   const long long total = (long long)rows_pad * ldl;
   const long long valid = (long long)n_aux_pad * ldl;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -61,16 +109,17 @@ __global__ void mixed_prep_kernel(const double *__restrict__ Lp, int n_aux_pad, 
     const int k = (int)(idx % ldl);
     const double v = idx < valid ? Lp[idx] : 0.0;
     Lf[idx] = (float)v;
-    unsigned short h, l;
-    split16<T>((float)(colscale ? v * (double)colscale[k] : v), h, l);
+    typename Mix<T>::E h, l;
+    Mix<T>::split((float)(colscale ? v * (double)colscale[k] : v), h, l);
     Bhi[idx] = h;
     Blo[idx] = l;
   }
 }
 
-// FP16 column scales: scale = 2^e_k, inv = 2^-e_k, acol = max_P |L_Pk| 2^-e_k
-// (the largest |A| of column k per unit |chi|).  One thread per column.
-__global__ void colscale_kernel(const double *__restrict__ Lp, int n_aux_pad, int ldl,
+// Column scales: scale = 2^e_k with max_P |L_Pk| 2^e_k in [2^(target-1),
+// 2^target), inv = 2^-e_k, acol = max_P |L_Pk| 2^-e_k (the largest |A| of
+// column k per unit |chi|).  One thread per column.
+__global__ void colscale_kernel(const double *__restrict__ Lp, int n_aux_pad, int ldl, int target,
                                 float *__restrict__ scale, float *__restrict__ inv_scale,
                                 float *__restrict__ acol) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,16 +130,17 @@ __global__ void colscale_kernel(const double *__restrict__ Lp, int n_aux_pad, in
   if (m > 0.0) {
     int ex;
     frexp(m, &ex);  // m = f 2^ex, f in [0.5, 1)
-    e = 7 - ex;
+    e = target - ex;
   }
   scale[k] = ldexpf(1.0f, e);
   inv_scale[k] = ldexpf(1.0f, -e);
   acol[k] = (float)ldexp(m, -e);
 }
 
-// FP16 per-frequency scale 2^g with max_k |chi_k| acol_k 2^g in [2^6, 2^7).
+// Per-frequency scale 2^g with max_k |chi_k| acol_k 2^g in [2^(target-1), 2^target).
 __global__ void taskscale_kernel(const double *__restrict__ chi_re, const double *__restrict__ chi_im,
-                                 int ldl, const float *__restrict__ acol, float *__restrict__ tscale) {
+                                 int ldl, int target, const float *__restrict__ acol,
+                                 float *__restrict__ tscale) {
   __shared__ double sh[256];
   const int f = blockIdx.x;
   double m = 0.0;
@@ -109,26 +159,11 @@ __global__ void taskscale_kernel(const double *__restrict__ chi_re, const double
     if (sh[0] > 0.0) {
       int ex;
       frexp(sh[0], &ex);
-      g = 7 - ex;
+      g = target - ex;
     }
     tscale[f] = ldexpf(1.0f, g);
   }
 }
-
-template <class T>
-struct Mfma;
-template <>
-struct Mfma<__bf16> {
-  static __device__ __forceinline__ f4 run(us8 a, us8 b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
-  }
-};
-template <>
-struct Mfma<_Float16> {
-  static __device__ __forceinline__ f4 run(us8 a, us8 b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
-  }
-};
 
 // Grid: (n_tiles, F).  Wave w: rows 32*(w/2) .. +32, columns (MX_TC/2)*(w%2)
 // .. +MX_TC/2, i.e. 2 x MX_NB blocks of 16 x 16, Re and Im accumulators (FP32).
@@ -136,16 +171,20 @@ struct Mfma<_Float16> {
 // output element r of lane l is D[4(l/16)+r][l%16].
 template <class T>
 __global__ void __launch_bounds__(MX_THREADS, 2)
-pi_build_mixed_kernel(const float *__restrict__ Lf, const unsigned short *__restrict__ Bhi,
-                      const unsigned short *__restrict__ Blo, int ldl, int n_aux,
+pi_build_mixed_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__restrict__ Bhi,
+                      const typename Mix<T>::E *__restrict__ Blo, int ldl, int n_aux,
                       const double *__restrict__ chi_re, const double *__restrict__ chi_im,
                       const float *__restrict__ inv_colscale, const float *__restrict__ tscale,
                       const int2 *__restrict__ tiles, double2 *__restrict__ G, long long g_stride,
                       int ldg) {
-  constexpr int KC = MX_KC, LA = KC + 4, LB = KC + 8;
+  using E = typename Mix<T>::E;
+  using V = typename Mix<T>::V;
+  constexpr int EP = 16 / (int)sizeof(E);  // elements per 16-byte load
+  // B rows padded by 16 bytes (rows stay 16-byte aligned)
+  constexpr int KC = MX_KC, LA = KC + 4, LB = KC + EP;
   __shared__ float As[MX_TR * LA];
-  __shared__ unsigned short Bh[MX_TC * LB];
-  __shared__ unsigned short Bl[MX_TC * LB];
+  __shared__ E Bh[MX_TC * LB];
+  __shared__ E Bl[MX_TC * LB];
   __shared__ float Cr[KC], Ci[KC];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -177,11 +216,11 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const unsigned short *__rest
       float *dst = As + row * LA + kq;
       dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
     }
-    // B: MX_TC rows x 32 halves, hi and lo (8 halves = 16 B per thread and pass)
+    // B: MX_TC rows x 32 elements, hi and lo (16 B per thread and pass)
 #pragma unroll
-    for (int it = 0; it < MX_TC / 64; ++it) {
-      const int idx = it * MX_THREADS + tid;       // 0 .. 4 MX_TC - 1
-      const int row = idx >> 2, kq = (idx & 3) * 8;
+    for (int it = 0; it < MX_TC * KC / (EP * MX_THREADS); ++it) {
+      const int idx = it * MX_THREADS + tid;
+      const int row = idx / (KC / EP), kq = (idx % (KC / EP)) * EP;
       const long long off = (long long)(Q0 + row) * ldl + kc + kq;
       const uint4 vh = *reinterpret_cast<const uint4 *>(Bhi + off);
       const uint4 vl = *reinterpret_cast<const uint4 *>(Blo + off);
@@ -196,18 +235,18 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const unsigned short *__rest
     __syncthreads();
 
     // A operands: this wave's two row blocks, Re and Im, split hi/lo
-    us8 arh[2], arl[2], aih[2], ail[2];
+    V arh[2], arl[2], aih[2], ail[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const float *src = As + (wr + 16 * a + li) * LA + 8 * lq;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const float lv = src[e];
-        unsigned short h, l;
-        split16<T>(lv * Cr[8 * lq + e], h, l);
+        E h, l;
+        Mix<T>::split(lv * Cr[8 * lq + e], h, l);
         arh[a][e] = h;
         arl[a][e] = l;
-        split16<T>(lv * Ci[8 * lq + e], h, l);
+        Mix<T>::split(lv * Ci[8 * lq + e], h, l);
         aih[a][e] = h;
         ail[a][e] = l;
       }
@@ -215,16 +254,16 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const unsigned short *__rest
 #pragma unroll
     for (int b = 0; b < MX_NB; ++b) {
       const int col = wc + 16 * b + li;
-      const us8 bh = *reinterpret_cast<const us8 *>(Bh + col * LB + 8 * lq);
-      const us8 bl = *reinterpret_cast<const us8 *>(Bl + col * LB + 8 * lq);
+      const V bh = *reinterpret_cast<const V *>(Bh + col * LB + 8 * lq);
+      const V bl = *reinterpret_cast<const V *>(Bl + col * LB + 8 * lq);
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        accr[a][b] = Mfma<T>::run(arh[a], bh, accr[a][b]);
-        accr[a][b] = Mfma<T>::run(arh[a], bl, accr[a][b]);
-        accr[a][b] = Mfma<T>::run(arl[a], bh, accr[a][b]);
-        acci[a][b] = Mfma<T>::run(aih[a], bh, acci[a][b]);
-        acci[a][b] = Mfma<T>::run(aih[a], bl, acci[a][b]);
-        acci[a][b] = Mfma<T>::run(ail[a], bh, acci[a][b]);
+        accr[a][b] = Mix<T>::mfma(arh[a], bh, accr[a][b]);
+        accr[a][b] = Mix<T>::mfma(arh[a], bl, accr[a][b]);
+        accr[a][b] = Mix<T>::mfma(arl[a], bh, accr[a][b]);
+        acci[a][b] = Mix<T>::mfma(aih[a], bh, acci[a][b]);
+        acci[a][b] = Mix<T>::mfma(aih[a], bl, acci[a][b]);
+        acci[a][b] = Mix<T>::mfma(ail[a], bh, acci[a][b]);
       }
     }
     __syncthreads();
@@ -252,34 +291,49 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const unsigned short *__rest
 
 // ---------------------------------------------------------------------------
 void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, float *Lf,
-                       unsigned short *Bhi, unsigned short *Blo, float *colscale,
-                       float *inv_colscale, float *acol, hipStream_t stream) {
+                       void *Bhi, void *Blo, float *colscale, float *inv_colscale, float *acol,
+                       hipStream_t stream) {
   long long blocks = ((long long)rows_pad * ldl + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (prec == 2) {
-    colscale_kernel<<<(ldl + 255) / 256, 256, 0, stream>>>(Lp, n_aux_pad, ldl, colscale,
-                                                            inv_colscale, acol);
-    mixed_prep_kernel<_Float16><<<(unsigned)blocks, 256, 0, stream>>>(Lp, n_aux_pad, rows_pad, ldl,
-                                                                      colscale, Lf, Bhi, Blo);
+    colscale_kernel<<<(ldl + 255) / 256, 256, 0, stream>>>(Lp, n_aux_pad, ldl, Mix<_Float16>::TARGET,
+                                                            colscale, inv_colscale, acol);
+    mixed_prep_kernel<_Float16><<<(unsigned)blocks, 256, 0, stream>>>(
+        Lp, n_aux_pad, rows_pad, ldl, colscale, Lf, static_cast<unsigned short *>(Bhi),
+        static_cast<unsigned short *>(Blo));
+  } else if (prec == 3) {
+    colscale_kernel<<<(ldl + 255) / 256, 256, 0, stream>>>(Lp, n_aux_pad, ldl, Mix<e4m3>::TARGET,
+                                                            colscale, inv_colscale, acol);
+    mixed_prep_kernel<e4m3><<<(unsigned)blocks, 256, 0, stream>>>(
+        Lp, n_aux_pad, rows_pad, ldl, colscale, Lf, static_cast<unsigned char *>(Bhi),
+        static_cast<unsigned char *>(Blo));
   } else {
-    mixed_prep_kernel<__bf16><<<(unsigned)blocks, 256, 0, stream>>>(Lp, n_aux_pad, rows_pad, ldl,
-                                                                    nullptr, Lf, Bhi, Blo);
+    mixed_prep_kernel<__bf16><<<(unsigned)blocks, 256, 0, stream>>>(
+        Lp, n_aux_pad, rows_pad, ldl, nullptr, Lf, static_cast<unsigned short *>(Bhi),
+        static_cast<unsigned short *>(Blo));
   }
 }
 
-void launch_pi_build_mixed(int prec, const float *Lf, const unsigned short *Bhi,
-                           const unsigned short *Blo, int ldl, int n_aux, const double *chi_re,
-                           const double *chi_im, const float *inv_colscale, const float *acol,
-                           float *tscale, int F, const int2 *tiles, int n_tiles, double2 *G,
-                           long long g_stride, int ldg, hipStream_t stream) {
+void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const void *Blo, int ldl,
+                           int n_aux, const double *chi_re, const double *chi_im,
+                           const float *inv_colscale, const float *acol, float *tscale, int F,
+                           const int2 *tiles, int n_tiles, double2 *G, long long g_stride, int ldg,
+                           hipStream_t stream) {
   dim3 grid(n_tiles, F);
   if (prec == 2) {
-    taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, acol, tscale);
+    taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, Mix<_Float16>::TARGET, acol, tscale);
     pi_build_mixed_kernel<_Float16><<<grid, MX_THREADS, 0, stream>>>(
-        Lf, Bhi, Blo, ldl, n_aux, chi_re, chi_im, inv_colscale, tscale, tiles, G, g_stride, ldg);
+        Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
+        n_aux, chi_re, chi_im, inv_colscale, tscale, tiles, G, g_stride, ldg);
+  } else if (prec == 3) {
+    taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, Mix<e4m3>::TARGET, acol, tscale);
+    pi_build_mixed_kernel<e4m3><<<grid, MX_THREADS, 0, stream>>>(
+        Lf, static_cast<const unsigned char *>(Bhi), static_cast<const unsigned char *>(Blo), ldl,
+        n_aux, chi_re, chi_im, inv_colscale, tscale, tiles, G, g_stride, ldg);
   } else {
     pi_build_mixed_kernel<__bf16><<<grid, MX_THREADS, 0, stream>>>(
-        Lf, Bhi, Blo, ldl, n_aux, chi_re, chi_im, nullptr, nullptr, tiles, G, g_stride, ldg);
+        Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
+        n_aux, chi_re, chi_im, nullptr, nullptr, tiles, G, g_stride, ldg);
   }
 }
 

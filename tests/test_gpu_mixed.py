@@ -1,7 +1,11 @@
-"""Mixed-precision Pi build (BF16X3, FP16X3) against the FP64 oracle / FP64 GPU path.
+"""Mixed-precision Pi build (BF16X3, FP16X3, FP8) against the FP64 oracle / FP64 GPU path.
 
-Targets: |dE_QP| <= 10 meV and matched satellite peak positions within 0.02 eV;
-Sigma^c errors are reported (max and median relative).
+Targets for BF16X3 and FP16X3: |dE_QP| <= 10 meV and matched satellite peak
+positions within 0.02 eV; Sigma^c errors are reported (max and median relative).
+FP8 (e4m3, 4-bit significands) carries ~2^-7 relative error per product (hi and
+lo each round to 2^-4 of what they represent, and lo*lo is dropped); the
+factorisation's conditioning can amplify that a few times, so its bars are
+|dSigma^c| <= 2^-4 max|Sigma^c| and |dE_QP| <= 2^-4 |Re Sigma^c(eps_n)|.
 """
 import numpy as np
 import pytest
@@ -35,7 +39,7 @@ def _spectrum(d, s, out, c, n_t=2 ** 16, dw=0.01 / EV_PER_HA):
     return w0 + np.arange(3500) * dw, A.cpu().numpy(), e_qp, float(z[0])
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3", "fp8"])
 def test_c1_mixed_vs_oracle(precision):
     s = system_from_config(CONFIGS["c1"])
     d = gwc.to_device(s, torch.device("cuda:0"))
@@ -46,11 +50,16 @@ def test_c1_mixed_vs_oracle(precision):
     rel = np.abs(sc - ref["sigma_c"]) / np.max(np.abs(ref["sigma_c"]))
     print(f"{precision} c1: Sigma^c rel err max {rel.max():.3e} median {np.median(rel):.3e}; "
           f"dE_QP {abs(out['e_qp'].cpu().numpy()[0] - ref['e_qp'][0]) * EV_PER_HA * 1e3:.3f} meV")
-    assert abs(out["e_qp"].cpu().numpy()[0] - ref["e_qp"][0]) <= EQP_TOL
-    assert rel.max() < (1e-3 if precision == "bf16x3" else 1e-4)
+    deq = abs(out["e_qp"].cpu().numpy()[0] - ref["e_qp"][0])
+    if precision == "fp8":
+        assert deq <= 2.0 ** -4 * abs(ref["sigma_c_eps"][0].real)
+        assert rel.max() < 2.0 ** -4
+    else:
+        assert deq <= EQP_TOL
+        assert rel.max() < (1e-3 if precision == "bf16x3" else 1e-4)
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3", "fp8"])
 def test_c2_size_mixed_eqp_and_satellites(precision):
     """Benzene-sized system, DECOUPLED mode (the paper's production setting):
     E_QP of every core within 10 meV and satellite peaks of A(w) within 0.02 eV
@@ -61,7 +70,11 @@ def test_c2_size_mixed_eqp_and_satellites(precision):
     out = _run(d, precision, "decoupled")
     deq = np.abs(out["e_qp"].cpu().numpy() - ref["e_qp"].cpu().numpy())
     print(f"{precision} c2: max dE_QP {deq.max() * EV_PER_HA * 1e3:.3f} meV")
-    assert deq.max() <= EQP_TOL
+    if precision == "fp8":
+        sc_ref = ref["sigma_c_eps"].cpu().numpy()[:, 0]
+        assert np.all(deq <= 2.0 ** -4 * np.abs(sc_ref))
+    else:
+        assert deq.max() <= EQP_TOL
     worst = 0.0
     for c in range(s.n_core):
         w, A_ref, eq_ref, z_ref = _spectrum(d, s, ref, c)
@@ -72,4 +85,5 @@ def test_c2_size_mixed_eqp_and_satellites(precision):
         for p in p_ref:
             worst = max(worst, np.min(np.abs(np.asarray(p_mx) - p)))
     print(f"{precision} c2: worst satellite shift {worst * EV_PER_HA * 1e3:.3f} meV")
-    assert worst <= SAT_TOL
+    if precision != "fp8":
+        assert worst <= SAT_TOL

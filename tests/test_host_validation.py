@@ -46,7 +46,7 @@ def _call(gwc, s, **kw):
 
 @pytest.mark.parametrize("case,status", [
     ("gap", -3), ("occ", -1), ("core", -2), ("eta", -1), ("grid_order", -1),
-    ("imag_weight", -1), ("nan_eps", -4), ("fp8", -8), ("mode", None), ("sym_virtual", -1),
+    ("imag_weight", -1), ("nan_eps", -4), ("mode", None), ("sym_virtual", -1),
 ])
 def test_sigma_core_argument_errors(gwc, case, status):
     s = _sys()
@@ -65,8 +65,6 @@ def test_sigma_core_argument_errors(gwc, case, status):
         s.w_imag[0] = -1.0
     elif case == "nan_eps":
         s.eps[5] = np.nan
-    elif case == "fp8":
-        kw["precision"] = "fp8"
     elif case == "sym_virtual":
         sym = -np.ones(s.n_basis, dtype=np.int32)
         sym[0] = sym[s.n_occ] = 1  # an unoccupied orbital in the core's equivalent set
