@@ -108,6 +108,20 @@ typedef struct {
   double delta_lower, delta_upper;
 } gwc_wac_params;
 
+/* Newton solution of the G0W0 quasiparticle equation (Eq. quasiparticle_equation)
+ *   E = eps_n + Sigma^x_n + Re Sigma^c_n(E) - v^xc_n
+ * from E = eps_n: f(E) = E - eps_n - Sigma^x_n - Re Sigma^c_n(E) + v^xc_n,
+ * f'(E) from the centred difference (f(E + step) - f(E - step)) / (2 step),
+ * E <- E - f(E) / f'(E), until |Delta E| < tol or max_iter steps.  Every
+ * iteration evaluates Sigma^c_n by contour deformation at E - step, E, E + step
+ * (the imaginary-axis W is computed once).  Constraints: max_iter >= 1,
+ * tol > 0, step > 0, finite (GWC_ERR_INVALID_ARG / GWC_ERR_NONFINITE). */
+typedef struct {
+  int32_t max_iter;
+  double tol;
+  double step;
+} gwc_qp_params;
+
 /* Arguments of gwc_sigma_core.
  *   core_idx   [n_core]          occupied states n (each < n_occ), the "core states"
  *   omega_imag [n_imag], w_imag  nodes (> 0, strictly increasing) and weights (> 0)
@@ -125,7 +139,10 @@ typedef struct {
  *              occupied orbitals only (GWC_ERR_INVALID_ARG otherwise).  It
  *              selects the residues of Im Sigma^dec.
  *   wac        NULL: contour deformation, every residue W from its own
- *              factorisation; else CD-WAC with these settings (host memory) */
+ *              factorisation; else CD-WAC with these settings (host memory)
+ *   qp         NULL, or the settings of the Newton quasiparticle solve (host
+ *              memory; contour deformation only: with wac set it returns
+ *              GWC_ERR_UNSUPPORTED) */
 typedef struct {
   int32_t n_core;
   const int32_t *core_idx;
@@ -140,6 +157,7 @@ typedef struct {
   int32_t precision;
   const int32_t *sym_group;
   const gwc_wac_params *wac;
+  const gwc_qp_params *qp;
 } gwc_sigma_args;
 
 /* Outputs of gwc_sigma_core (each may be host or device memory).
@@ -152,13 +170,20 @@ typedef struct {
  *   sigma_c_eps  [n_core][2]          Sigma^c_n(eps_n) (re, im), or NULL
  *   sigma_x      [n_core]             Sigma^x_n = -sum_i (n i|i n), or NULL
  *   e_qp         [n_core]             E_QP = eps_n + Sigma^x_n + Re Sigma^c_n(eps_n) - v^xc_n
- *                                     (Eq. QPGWC), or NULL */
+ *                                     (Eq. QPGWC), or NULL
+ *   e_qp_newton  [n_core]             with args->qp: the Newton solution of Eq.
+ *                                     quasiparticle_equation (the last iterate when it
+ *                                     did not converge), or NULL
+ *   qp_iterations [n_core] int32      with args->qp: Newton steps taken, -1 when
+ *                                     max_iter steps did not converge, or NULL */
 typedef struct {
   double *sigma_c;
   double *im_sigma_dec;
   double *sigma_c_eps;
   double *sigma_x;
   double *e_qp;
+  double *e_qp_newton;
+  int32_t *qp_iterations;
 } gwc_sigma_out;
 
 /* Correlation self-energy of the requested core states by contour

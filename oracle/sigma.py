@@ -202,8 +202,34 @@ def sigma_c_at(L, delta, eps, occ, M_oo, M_ov, n, omega, eta, Wn, omega_imag, w_
     return -I + R, im_dec, terms
 
 
+def qp_newton(L, delta, eps, occ, M_oo, M_ov, n, eta, Wn, omega_imag, w_imag, vxc=0.0,
+              max_iter=30, tol=1e-8, step=1e-4):
+    """The G0W0 quasiparticle equation (Eq. quasiparticle_equation),
+    E = eps_n + Sigma^x_n + Re Sigma^c_n(E) - v^xc_n, by Newton's method from
+    E = eps_n with the derivative from a centred difference of step h:
+    f(E) = E - eps_n - Sigma^x_n - Re Sigma^c_n(E) + v^xc_n,
+    f'(E) ~ (f(E + h) - f(E - h)) / (2 h),  E <- E - f(E) / f'(E),
+    stopping when |Delta E| < tol.  Returns (E, iterations), iterations = -1 when
+    max_iter steps did not converge (E is then the last iterate)."""
+    sx = exchange(M_oo, n)
+    en = float(eps[n])
+
+    def f(E):
+        sc, _, _ = sigma_c_at(L, delta, eps, occ, M_oo, M_ov, n, E, eta, Wn, omega_imag, w_imag)
+        return E - en - sx - sc.real + vxc
+
+    E = en
+    for it in range(1, max_iter + 1):
+        fm, f0, fp = f(E - step), f(E), f(E + step)
+        dE = -f0 / ((fp - fm) / (2.0 * step))
+        E = E + dE
+        if abs(dE) < tol:
+            return E, it
+    return E, -1
+
+
 def sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_real, eta,
-               vxc=None, mode: str = "full", sym_group=None):
+               vxc=None, mode: str = "full", sym_group=None, qp=None):
     """Full oracle for the `gwc_sigma_core` entry point.
 
     mode "full": Sigma^c_n on every real grid point (all residue terms);
@@ -211,7 +237,9 @@ def sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_real, e
     (gives ImSigma^dec; the set is [n] unless sym_group labels equivalent core
     levels), plus the full Sigma^c_n(eps_n) for E_QP.  Returns a dict with sigma_c
     [n_core][n_real] complex (None in decoupled mode), im_sigma_dec
-    [n_core][n_real], sigma_c_eps [n_core] complex, sigma_x, e_qp [n_core]."""
+    [n_core][n_real], sigma_c_eps [n_core] complex, sigma_x, e_qp [n_core]; with
+    qp = dict(max_iter, tol, step) also e_qp_newton and qp_iterations [n_core]
+    (the G0W0 quasiparticle equation by Newton's method, qp_newton)."""
     eps = np.asarray(eps, dtype=float)
     occ = np.asarray(occ, dtype=float)
     n_occ = M_oo.shape[1]
@@ -245,15 +273,22 @@ def sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_real, e
         sigma_c_eps[c] = s_eps
         sigma_x[c] = exchange(M_oo, n)
         e_qp[c] = float(eps[n]) + sigma_x[c] + float(np.real(s_eps)) - vxc[c]
-    return dict(sigma_c=sigma_c, im_sigma_dec=im_dec, sigma_c_eps=sigma_c_eps,
-                sigma_x=sigma_x, e_qp=e_qp, w_imag=W)
+    out = dict(sigma_c=sigma_c, im_sigma_dec=im_dec, sigma_c_eps=sigma_c_eps,
+               sigma_x=sigma_x, e_qp=e_qp, w_imag=W)
+    if qp is not None:
+        res = [qp_newton(L, delta, eps, occ, M_oo, M_ov, n, eta, W[c], omega_imag, w_imag,
+                         float(vxc[c]), qp["max_iter"], qp["tol"], qp["step"])
+               for c, n in enumerate(cores)]
+        out["e_qp_newton"] = np.array([r[0] for r in res])
+        out["qp_iterations"] = np.array([r[1] for r in res])
+    return out
 
 
-def sigma_core_system(sys, mode: str = "full", sym_group=None):
+def sigma_core_system(sys, mode: str = "full", sym_group=None, qp=None):
     """Convenience wrapper taking an object with the ABI's fields as attributes."""
     return sigma_core(sys.eps, sys.occ, sys.M_oo, sys.M_ov, sys.core_idx, sys.omega_imag,
                       sys.w_imag, sys.omega_real, sys.eta, vxc=getattr(sys, "vxc", None),
-                      mode=mode, sym_group=sym_group)
+                      mode=mode, sym_group=sym_group, qp=qp)
 
 
 def count_residue_tasks(eps, occ, core_idx, omega_real, mode: str = "full",

@@ -61,6 +61,10 @@ class GwcWacParams(Structure):
     ]
 
 
+class GwcQpParams(Structure):
+    _fields_ = [("max_iter", c_int32), ("tol", c_double), ("step", c_double)]
+
+
 class GwcSigmaArgs(Structure):
     _fields_ = [
         ("n_core", c_int32), ("core_idx", c_void_p),
@@ -68,14 +72,15 @@ class GwcSigmaArgs(Structure):
         ("n_real", c_int32), ("omega_real", c_void_p),
         ("eta", c_double), ("vxc", c_void_p),
         ("mode", c_int32), ("precision", c_int32),
-        ("sym_group", c_void_p), ("wac", c_void_p),
+        ("sym_group", c_void_p), ("wac", c_void_p), ("qp", c_void_p),
     ]
 
 
 class GwcSigmaOut(Structure):
     _fields_ = [
         ("sigma_c", c_void_p), ("im_sigma_dec", c_void_p), ("sigma_c_eps", c_void_p),
-        ("sigma_x", c_void_p), ("e_qp", c_void_p),
+        ("sigma_x", c_void_p), ("e_qp", c_void_p), ("e_qp_newton", c_void_p),
+        ("qp_iterations", c_void_p),
     ]
 
 

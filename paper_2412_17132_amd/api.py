@@ -51,21 +51,24 @@ def _stream_handle(stream):
     return None
 
 
-def _alloc(shape, like):
+def _alloc(shape, like, integer=False):
     if _is_tensor(like) and like.is_cuda:
         torch = _torch()
-        return torch.empty(shape, dtype=torch.float64, device=like.device)
-    return np.empty(shape, dtype=np.float64)
+        return torch.empty(shape, dtype=torch.int32 if integer else torch.float64, device=like.device)
+    return np.empty(shape, dtype=np.int32 if integer else np.float64)
 
 
 def gwc_sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_real, eta,
                    vxc=None, mode: str = "full", precision: str = "fp64",
-                   out: Optional[dict] = None, stream=None, sym_group=None, wac=None) -> dict:
+                   out: Optional[dict] = None, stream=None, sym_group=None, wac=None,
+                   qp=None) -> dict:
     """Sigma^c_n(w) of the core states by contour deformation (gwc_sigma_core).
 
     sym_group: optional [n_basis] int32 labels of symmetry-equivalent core levels.
     wac: optional dict of CD-WAC settings (n_core_pts, core_min, core_max,
     n_val_pts, delta_lower, delta_upper; Hartree) -- CD-WAC instead of CD.
+    qp: optional dict (max_iter, tol, step; Hartree) -- also solve the G0W0
+    quasiparticle equation by Newton's method (e_qp_newton, qp_iterations).
     Returns a dict with sigma_c [n_core][n_real][2] (None in decoupled mode),
     im_sigma_dec [n_core][n_real], sigma_c_eps [n_core][2], sigma_x, e_qp."""
     lib = N.load()
@@ -80,7 +83,7 @@ def gwc_sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_rea
                           _as_arg(omega_imag, "f8", keep), _as_arg(w_imag, "f8", keep), n_real,
                           _as_arg(omega_real, "f8", keep), float(eta), _as_arg(vxc, "f8", keep),
                           N.MODES[mode], N.PRECISIONS[precision], _as_arg(sym_group, "i4", keep),
-                          wac_arg(wac, keep))
+                          wac_arg(wac, keep), qp_arg(qp, keep))
     if out is None:
         out = {
             "sigma_c": _alloc((n_core, n_real, 2), M_ov) if mode == "full" else None,
@@ -89,8 +92,12 @@ def gwc_sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_rea
             "sigma_x": _alloc((n_core,), M_ov),
             "e_qp": _alloc((n_core,), M_ov),
         }
+        if qp is not None:
+            out["e_qp_newton"] = _alloc((n_core,), M_ov)
+            out["qp_iterations"] = _alloc((n_core,), M_ov, integer=True)
     o = N.GwcSigmaOut(*(_as_out(out.get(k)) for k in
-                        ("sigma_c", "im_sigma_dec", "sigma_c_eps", "sigma_x", "e_qp")))
+                        ("sigma_c", "im_sigma_dec", "sigma_c_eps", "sigma_x", "e_qp",
+                         "e_qp_newton", "qp_iterations")))
     N.check(lib.gwc_sigma_core(sys, args, o, _stream_handle(stream)))
     return out
 
@@ -101,6 +108,16 @@ def wac_paper_settings(n_core_pts: int = 100, n_val_pts: int = 100) -> dict:
     and 1 % above; energies in Hartree."""
     return dict(n_core_pts=n_core_pts, core_min=0.0, core_max=40.0 / 27.211386245988,
                 n_val_pts=n_val_pts, delta_lower=0.08, delta_upper=0.01)
+
+
+def qp_arg(qp, keep: list):
+    """Pointer to a gwc_qp_params built from a dict (None: no Newton solve)."""
+    if qp is None:
+        return None
+    import ctypes
+    p = N.GwcQpParams(int(qp["max_iter"]), float(qp["tol"]), float(qp["step"]))
+    keep.append(p)
+    return ctypes.addressof(p)
 
 
 def wac_arg(wac, keep: list):
@@ -118,9 +135,9 @@ def _as_out(x):
     if x is None:
         return None
     if _is_tensor(x):
-        assert x.dtype == _torch().float64 and x.is_contiguous()
+        assert x.dtype in (_torch().float64, _torch().int32) and x.is_contiguous()
         return x.data_ptr()
-    assert x.dtype == np.float64 and x.flags["C_CONTIGUOUS"]
+    assert x.dtype in (np.float64, np.int32) and x.flags["C_CONTIGUOUS"]
     return x.ctypes.data
 
 

@@ -484,6 +484,8 @@ struct SigmaInputs {
   std::vector<std::vector<int>> sym;  // per core: its equivalent set, ascending
   bool wac = false;
   gwc_wac_params wp{};
+  bool qp = false;
+  gwc_qp_params qpp{};
 };
 
 SigmaInputs check_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
@@ -535,6 +537,15 @@ SigmaInputs check_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
       fail(GWC_ERR_INVALID_ARG, "CD-WAC core window must satisfy 0 <= core_min < core_max");
     if (!(w.delta_lower >= 0.0 && w.delta_lower < 1.0 && w.delta_upper >= 0.0))
       fail(GWC_ERR_INVALID_ARG, "CD-WAC margins must satisfy 0 <= delta_lower < 1, delta_upper >= 0");
+  }
+  if (args->qp) {
+    in.qp = true;
+    in.qpp = *args->qp;
+    const gwc_qp_params &q = in.qpp;
+    if (!std::isfinite(q.tol) || !std::isfinite(q.step)) fail(GWC_ERR_NONFINITE, "non-finite Newton setting");
+    if (q.max_iter < 1 || !(q.tol > 0.0) || !(q.step > 0.0))
+      fail(GWC_ERR_INVALID_ARG, "Newton settings need max_iter >= 1, tol > 0, step > 0");
+    if (args->wac) fail(GWC_ERR_UNSUPPORTED, "the Newton quasiparticle solve runs with contour deformation only");
   }
   std::vector<int> labels;
   if (args->sym_group) labels = to_host(args->sym_group, n_basis, s);
@@ -707,6 +718,96 @@ void run_wac(ResidentSystem &rs, const MixedOperands *mx, const gwc_sigma_args *
   if (flag) fail(GWC_ERR_FACTORIZATION, "CD-WAC continued-fraction fit broke down (zero reciprocal difference)");
 }
 
+// Newton solution of the quasiparticle equation (Eq. quasiparticle_equation)
+// for every core: per iteration Sigma^c at E - h, E, E + h by contour
+// deformation on the cores still iterating, then the update on the host.
+void run_qp_newton(ResidentSystem &rs, const MixedOperands *mx, const gwc_sigma_args *args,
+                   const SigmaInputs &in, const double2 *d_Wimag, const double *d_wi,
+                   const double *d_wwi, const std::vector<double> &sx, std::vector<double> &E,
+                   std::vector<int> &iters, std::vector<int> &status, hipStream_t s,
+                   size_t batch_bytes) {
+  const gwc_qp_params &q = in.qpp;
+  const int nc = args->n_core, ni = args->n_imag, nb = rs.nb;
+  E.resize(nc);
+  iters.assign(nc, -1);
+  std::vector<char> active(nc, 1);
+  for (int c = 0; c < nc; ++c) E[c] = rs.eps[in.core[c]];
+  for (int it = 1; it <= q.max_iter; ++it) {
+    std::vector<int> idx;
+    for (int c = 0; c < nc; ++c)
+      if (active[c]) idx.push_back(c);
+    if (idx.empty()) break;
+    const int na = (int)idx.size();
+    SigmaInputs sub;
+    sub.wi = in.wi;
+    sub.wwi = in.wwi;
+    std::vector<double> sxa(na);
+    for (int k = 0; k < na; ++k) {
+      const int c = idx[k];
+      sub.core.push_back(in.core[c]);
+      sub.vxc.push_back(in.vxc[c]);
+      sub.sym.push_back({in.core[c]});
+      sxa[k] = sx[c];
+      sub.wr.push_back(E[c] - q.step);
+      sub.wr.push_back(E[c]);
+      sub.wr.push_back(E[c] + q.step);
+    }
+    gwc_sigma_args sa = *args;
+    sa.n_core = na;
+    sa.n_real = 3;
+    sa.mode = GWC_MODE_FULL;
+    TaskList tr;
+    std::vector<double> ftask;
+    std::vector<int> cj_off, tdec;
+    build_residue_tasks(rs, &sa, sub, tr, ftask, cj_off, tdec);
+    DevBuf dW(s), dWr(s), dcore(s), dwr(s), dsx(s), dvxc(s), dI(s), dft(s), dcjo(s), dtd(s);
+    DevBuf dsig(s), dimd(s), dse(s), deq(s);
+    dW.alloc((size_t)na * nb * ni * sizeof(double2));
+    for (int k = 0; k < na; ++k)
+      HIPCHECK(hipMemcpyAsync(dW.as<double2>() + (size_t)k * nb * ni, d_Wimag + (size_t)idx[k] * nb * ni,
+                              (size_t)nb * ni * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    dWr.alloc(std::max<size_t>(tr.size(), 1) * sizeof(double2));
+    run_screening(rs, mx, args->precision, tr, 1, dWr.as<double2>(), status, s, batch_bytes);
+    for (int v : status)
+      if (v) fail(GWC_ERR_FACTORIZATION, "exactly singular pivot in the LU of 1 - Pi(z)");
+    const int *d_core = upload(dcore, sub.core, s);
+    const double *d_wr = upload(dwr, sub.wr, s);
+    const double *d_sx = upload(dsx, sxa, s);
+    const double *d_vxc = upload(dvxc, sub.vxc, s);
+    dI.alloc((size_t)na * 4 * sizeof(double));
+    launch_quadrature(dW.as<double2>(), rs.d_eps.as<double>(), nb, d_wi, d_wwi, ni, d_wr, 3, d_core, na,
+                      4, dI.as<double>(), s);
+    const double *d_f = upload(dft, ftask, s);
+    const int *d_cjo = upload(dcjo, cj_off, s);
+    const int *d_td = upload(dtd, tdec, s);
+    dsig.alloc((size_t)na * 3 * 2 * sizeof(double));
+    dimd.alloc((size_t)na * 3 * sizeof(double));
+    dse.alloc((size_t)na * 2 * sizeof(double));
+    deq.alloc((size_t)na * sizeof(double));
+    launch_assemble(dWr.as<double2>(), d_f, d_td, d_cjo, dI.as<double>(), na, 3, rs.d_eps.as<double>(),
+                    d_core, d_sx, d_vxc, 1, dsig.as<double>(), dimd.as<double>(), dse.as<double>(),
+                    deq.as<double>(), s);
+    HIPCHECK(hipGetLastError());
+    std::vector<double> sig((size_t)na * 6);
+    HIPCHECK(hipMemcpyAsync(sig.data(), dsig.p, sig.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int k = 0; k < na; ++k) {
+      const int c = idx[k];
+      const double en = rs.eps[in.core[c]];
+      const double Em = E[c] - q.step, Ep = E[c] + q.step;
+      const double fm = Em - en - sx[c] - sig[(size_t)k * 6 + 0] + in.vxc[c];
+      const double f0 = E[c] - en - sx[c] - sig[(size_t)k * 6 + 2] + in.vxc[c];
+      const double fp = Ep - en - sx[c] - sig[(size_t)k * 6 + 4] + in.vxc[c];
+      const double dE = -f0 / ((fp - fm) / (2.0 * q.step));
+      E[c] = E[c] + dE;
+      if (std::fabs(dE) < q.tol) {
+        active[c] = 0;
+        iters[c] = it;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 void validate_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
@@ -809,6 +910,17 @@ void run_sigma(ResidentSystem &rs, const gwc_sigma_args *args, gwc_sigma_out *ou
   copy_out(out->sigma_c_eps, dse.p, (size_t)nc * 2 * sizeof(double), s);
   copy_out(out->sigma_x, dsx.p, (size_t)nc * sizeof(double), s);
   copy_out(out->e_qp, deq.p, (size_t)nc * sizeof(double), s);
+  std::vector<double> e_newton;
+  std::vector<int> qp_it;
+  if (in.qp) {
+    std::vector<double> sx(nc);
+    HIPCHECK(hipMemcpyAsync(sx.data(), dsx.p, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    run_qp_newton(rs, mx, args, in, dWi.as<double2>(), d_wi, d_wwi, sx, e_newton, qp_it, status, s,
+                  batch_bytes);
+    copy_out(out->e_qp_newton, e_newton.data(), (size_t)nc * sizeof(double), s);
+    copy_out(out->qp_iterations, qp_it.data(), (size_t)nc * sizeof(int), s);
+  }
   HIPCHECK(hipStreamSynchronize(s));
 }
 

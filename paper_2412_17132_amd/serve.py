@@ -8,7 +8,7 @@ import ctypes
 import numpy as np
 
 from . import _native as N
-from .api import _as_arg, _as_out, _stream_handle, wac_arg
+from .api import _as_arg, _as_out, _stream_handle, qp_arg, wac_arg
 
 
 class ResidentSystem:
@@ -31,7 +31,7 @@ class ResidentSystem:
         return cls(s.eps, s.occ, s.M_oo, s.M_ov)
 
     def sigma_core(self, core_idx, omega_imag, w_imag, omega_real, eta, vxc=None, mode="full",
-                   precision="fp64", stream=None, sym_group=None, wac=None):
+                   precision="fp64", stream=None, sym_group=None, wac=None, qp=None):
         """gwc_sigma_core_resident; outputs as NumPy arrays."""
         lib = N.load()
         keep: list = []
@@ -43,7 +43,7 @@ class ResidentSystem:
                               _as_arg(omega_imag, "f8", keep), _as_arg(w_imag, "f8", keep), n_real,
                               _as_arg(omega_real, "f8", keep), float(eta), _as_arg(vxc, "f8", keep),
                               N.MODES[mode], N.PRECISIONS[precision], _as_arg(sym_group, "i4", keep),
-                              wac_arg(wac, keep))
+                              wac_arg(wac, keep), qp_arg(qp, keep))
         out = {
             "sigma_c": np.empty((n_core, n_real, 2)) if mode == "full" else None,
             "im_sigma_dec": np.empty((n_core, n_real)),
@@ -51,8 +51,12 @@ class ResidentSystem:
             "sigma_x": np.empty(n_core),
             "e_qp": np.empty(n_core),
         }
+        if qp is not None:
+            out["e_qp_newton"] = np.empty(n_core)
+            out["qp_iterations"] = np.empty(n_core, dtype=np.int32)
         o = N.GwcSigmaOut(*(_as_out(out.get(k)) for k in
-                            ("sigma_c", "im_sigma_dec", "sigma_c_eps", "sigma_x", "e_qp")))
+                            ("sigma_c", "im_sigma_dec", "sigma_c_eps", "sigma_x", "e_qp",
+                             "e_qp_newton", "qp_iterations")))
         N.check(lib.gwc_sigma_core_resident(self.handle, args, o, _stream_handle(stream)))
         return out
 

@@ -163,3 +163,34 @@ def test_symmetric_decoupling(mode):
     torch.cuda.synchronize()
     out = {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
     _compare(out, OS.sigma_core_system(s, mode=mode, sym_group=sym), mode)
+
+
+@pytest.mark.parametrize("name", ["c1", "small"])
+def test_qp_newton(name):
+    """Newton solution of the quasiparticle equation: same root as the oracle
+    (each Sigma^c evaluation agrees to 1e-9, so the roots agree to well below
+    1e-8 Ha) and the same number of steps up to one (a step that lands near the
+    tolerance may stop one step apart); max_iter = 1 reports non-convergence."""
+    if name == "c1":
+        s = system_from_config(CONFIGS["c1"])
+    else:
+        s = system_from_config(small_config(n_occ=4, n_virt=9, n_aux=65, n_core=2, n_real=4,
+                                            seed=14))
+        s.vxc = np.array([-0.3, -0.25])
+    qp = dict(max_iter=40, tol=1e-9, step=1e-4)
+    print(f"case qp newton {name}", flush=True)
+    d = gwc.to_device(s, _dev())
+    out = gwc.gwc_sigma_core(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],
+                             d["omega_imag"], d["w_imag"], d["omega_real"], d["eta"], vxc=d["vxc"],
+                             mode="decoupled", qp=qp)
+    torch.cuda.synchronize()
+    ref = OS.sigma_core_system(s, mode="decoupled", qp=qp)
+    e = out["e_qp_newton"].cpu().numpy()
+    it = out["qp_iterations"].cpu().numpy()
+    print(f"E_newton {e} iterations {it}; oracle {ref['e_qp_newton']} {ref['qp_iterations']}")
+    assert np.all(np.abs(e - ref["e_qp_newton"]) < 1e-8)
+    assert np.all(it > 0) and np.all(np.abs(it - ref["qp_iterations"]) <= 1)
+    one = gwc.gwc_sigma_core(s.eps, s.occ, s.M_oo, s.M_ov, s.core_idx, s.omega_imag, s.w_imag,
+                             s.omega_real, s.eta, vxc=s.vxc, mode="decoupled",
+                             qp=dict(max_iter=1, tol=1e-300, step=1e-4))
+    assert np.all(one["qp_iterations"] == -1)

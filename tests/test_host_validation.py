@@ -120,3 +120,17 @@ def test_wac_argument_errors(gwc):
         with pytest.raises(gwc.GwcError) as ei:
             _call(gwc, s, wac=p)
         assert ei.value.status == status, (p, str(ei.value))
+
+
+def test_qp_newton_argument_errors(gwc):
+    from oracle import wac as OW
+    s = _sys()
+    for qp, status in ((dict(max_iter=0, tol=1e-8, step=1e-4), -1),
+                       (dict(max_iter=5, tol=-1.0, step=1e-4), -1),
+                       (dict(max_iter=5, tol=1e-8, step=float("inf")), -4)):
+        with pytest.raises(gwc.GwcError) as ei:
+            _call(gwc, s, qp=qp)
+        assert ei.value.status == status, (qp, str(ei.value))
+    with pytest.raises(gwc.GwcError) as ei:
+        _call(gwc, s, qp=dict(max_iter=5, tol=1e-8, step=1e-4), wac=OW.paper_params())
+    assert ei.value.status == -8

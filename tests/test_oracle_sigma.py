@@ -311,3 +311,46 @@ def test_symmetric_decoupling_defaults_and_full_mode():
     bad[s.n_occ] = 3  # a virtual orbital in the set
     with pytest.raises(ValueError):
         S.sigma_core_system(s, mode="decoupled", sym_group=bad)
+
+
+# --- the quasiparticle equation ---------------------------------------------------
+
+def test_qp_newton_matches_one_pole_roots():
+    """With the one-mode model, Sigma^c(w) = rho^2/(w - eps_c + Omega), the
+    quasiparticle equation (Eq. quasiparticle_equation) is the quadratic
+    x^2 + (Omega - s) x - (s Omega + rho^2) = 0 in x = E - eps_c, s = Sigma^x - v^xc.
+    Its upper root is the QP solution and the lower one the satellite solution
+    (the paper's two graphical solutions); Newton from eps_c finds the upper."""
+    eps = np.array([-10.6, -0.9, 0.3])
+    occ = np.array([2.0, 2.0, 0.0])
+    mval, bcc = 0.45, 0.8
+    M_ov = np.zeros((1, 2, 1))
+    M_ov[0, 1, 0] = mval
+    M_oo = np.zeros((1, 2, 2))
+    M_oo[0, 0, 0] = bcc
+    M_oo[0, 1, 1] = 0.3
+    L, d = S.ov_matrix(M_ov), S.transition_energies(eps, 2)
+    D = eps[2] - eps[1]
+    Om = np.sqrt(D * D + 4 * mval * mval * D)
+    rho2 = 2 * bcc * bcc * mval * mval * D / Om
+    x, w = mgl_grid(400, 0.5)
+    W = S.w_imag_axis(L, d, M_oo, M_ov, [0], x)
+    for vxc in (0.0, -0.35):
+        s = -bcc * bcc - vxc
+        bq, cq = Om - s, -(s * Om + rho2)
+        roots = np.sort(np.roots([1.0, bq, cq]).real)
+        E, it = S.qp_newton(L, d, eps, occ, M_oo, M_ov, 0, 1e-10, W[0], x, w, vxc=vxc,
+                            max_iter=40, tol=1e-12, step=1e-5)
+        assert it > 0
+        assert abs(E - (eps[0] + roots[1])) < 1e-8
+        # the satellite root also solves the equation
+        sc, _, _ = S.sigma_c_at(L, d, eps, occ, M_oo, M_ov, 0, eps[0] + roots[0], 1e-10, W[0], x, w)
+        assert abs(roots[0] - (s + sc.real)) < 1e-8
+
+
+def test_qp_newton_reports_non_convergence():
+    s = _tiny(seed=83, n_real=3)
+    out = S.sigma_core_system(s, qp=dict(max_iter=1, tol=1e-300, step=1e-4))
+    assert out["qp_iterations"][0] == -1
+    conv = S.sigma_core_system(s, qp=dict(max_iter=50, tol=1e-10, step=1e-4))
+    assert conv["qp_iterations"][0] > 1
