@@ -18,12 +18,19 @@ Contents
                (section "Numerical GW+C scheme", Eqs. landau_cumulant_truncated,
                cumulant_propagator_numerical_time, cumulant_propagator_fourier,
                cumulant_propagator_convolution, eq:AGWC).
+* `wac`      - CD-WAC: W^c_nm continued from reference points by a Thiele
+               continued fraction (Eq. pade_approximation).
+* `analytic` - the fully analytic G0W0 route: RPA excitations from the
+               Casida problem (Eqs. rpa_casida, rpa_matrices), transition
+               moments (Eq. density_shifts), the pole sum of Eq. sigma_spectral
+               and the G0W0 / G_DH W0 spectral functions (Eqs.
+               A_explicit_real_imaginary, hedin_sigma_spectral).
 
 Parity status of every function is stated in its docstring; none is
 "parity unpinned" (each is pinned by tests under `tests/test_oracle_*.py`).
 """
-from . import cumulant, sigma  # noqa: F401
+from . import analytic, cumulant, sigma, wac  # noqa: F401
 from .cumulant import spectral_cumulant
 from .sigma import sigma_core
 
-__all__ = ["sigma", "cumulant", "sigma_core", "spectral_cumulant"]
+__all__ = ["sigma", "cumulant", "wac", "analytic", "sigma_core", "spectral_cumulant"]
