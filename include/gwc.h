@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define GWC_VERSION 10100 /* 1.1.0 */
+#define GWC_VERSION 10200 /* 1.2.0 */
 
 enum gwc_status {
   GWC_OK = 0,
@@ -233,6 +233,61 @@ typedef struct {
  * Returns GWC_OK or a negative gwc_status. */
 int gwc_spectral_cumulant(const gwc_cumulant_args *args, double *A_out, double *z_out,
                           void *hip_stream);
+
+/* Arguments of gwc_sigma_analytic.
+ *   core_idx   [n_core]         occupied states n (each < n_occ)
+ *   omega_real [n_core][n_real] real frequencies per core state, strictly increasing
+ *   eta        > 0              broadening of the poles (Eq. sigma_spectral)
+ *   vxc        [n_core] or NULL <n|v_xc|n>, NULL means 0 */
+typedef struct {
+  int32_t n_core;
+  const int32_t *core_idx;
+  int32_t n_real;
+  const double *omega_real;
+  double eta;
+  const double *vxc;
+} gwc_analytic_args;
+
+/* Outputs of gwc_sigma_analytic (each may be host or device memory).
+ *   sigma_c     [n_core][n_real][2]  Sigma^c_n(w) (re, im), Eq. sigma_spectral (required)
+ *   sigma_c_eps [n_core][2]          Sigma^c_n(eps_n), or NULL
+ *   sigma_x     [n_core]             Sigma^x_n = -sum_i (n i|i n), or NULL
+ *   e_qp        [n_core]             eps_n + Sigma^x_n + Re Sigma^c_n(eps_n) - v^xc_n (Eq.
+ *                                    QPGWC); DH_n = e_qp - eps_n is the Hedin shift (Eq.
+ *                                    hedin_shift), or NULL
+ *   a_gw        [n_core][n_real]     A^G0W0_n(w) of Eq. A_explicit_real_imaginary, or NULL
+ *   a_dh        [n_core][n_real]     A^{G_DH W0}_n at w + DH_n, i.e. with Sigma^c_n(w) and
+ *                                    w - eps_n replaced by w + DH_n - eps_n (Eq.
+ *                                    hedin_sigma_spectral), or NULL
+ *   omega_exc   [n_occ * n_virt]     RPA excitation energies Omega^nu ascending, or NULL
+ *   sweeps      [1] int32            block-Jacobi sweeps taken, or NULL */
+typedef struct {
+  double *sigma_c;
+  double *sigma_c_eps;
+  double *sigma_x;
+  double *e_qp;
+  double *a_gw;
+  double *a_dh;
+  double *omega_exc;
+  int32_t *sweeps;
+} gwc_analytic_out;
+
+/* Fully analytic G0W0 self-energy of the requested core states (paper section
+ * "GW for core levels"):
+ *   RPA excitations from Eqs. rpa_casida, rpa_matrices for real orbitals, closed-shell
+ *   singlet, in the symmetric form C Z = Omega^2 Z with
+ *     C = Delta^2 + 4 Delta^1/2 K Delta^1/2,  K_ia,jb = (ia|jb) = sum_P M^P_ia M^P_jb,
+ *     X + Y = Delta^1/2 Z Omega^-1/2;
+ *   rho^nu_nm = sqrt(2) sum_ia (nm|ia) (X + Y)^nu_ia            (Eq. density_shifts)
+ *   Sigma^c_n(w) = sum_{m,nu} (rho^nu_nm)^2 /
+ *                  (w - eps_m + (Omega^nu - i eta) sgn(eps_F - eps_m))  (Eq. sigma_spectral)
+ * C is diagonalised on the device by cyclic block Jacobi (converged when a sweep
+ * applies no rotation larger than the working precision; more than 60 sweeps
+ * return GWC_ERR_FACTORIZATION).  Device memory ~ 8 (n_ov^2 + 3 n_aux n_ov +
+ * n_core n_basis (n_aux + n_ov)) bytes, n_ov = n_occ * n_virt <= 65536
+ * (GWC_ERR_SHAPE otherwise).  Returns GWC_OK or a negative gwc_status. */
+int gwc_sigma_analytic(const gwc_system *sys, const gwc_analytic_args *args, gwc_analytic_out *out,
+                       void *hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Device-resident systems (serving form).  gwc_system_create validates a

@@ -44,6 +44,7 @@ EXPORTED_SYMBOLS = (
     "gwc_server_stats",
     "gwc_server_destroy",
     "gwc_probe_peak",
+    "gwc_sigma_analytic",
 )
 
 
@@ -81,6 +82,21 @@ class GwcSigmaOut(Structure):
         ("sigma_c", c_void_p), ("im_sigma_dec", c_void_p), ("sigma_c_eps", c_void_p),
         ("sigma_x", c_void_p), ("e_qp", c_void_p), ("e_qp_newton", c_void_p),
         ("qp_iterations", c_void_p),
+    ]
+
+
+class GwcAnalyticArgs(Structure):
+    _fields_ = [
+        ("n_core", c_int32), ("core_idx", c_void_p), ("n_real", c_int32),
+        ("omega_real", c_void_p), ("eta", c_double), ("vxc", c_void_p),
+    ]
+
+
+class GwcAnalyticOut(Structure):
+    _fields_ = [
+        ("sigma_c", c_void_p), ("sigma_c_eps", c_void_p), ("sigma_x", c_void_p),
+        ("e_qp", c_void_p), ("a_gw", c_void_p), ("a_dh", c_void_p), ("omega_exc", c_void_p),
+        ("sweeps", c_void_p),
     ]
 
 
@@ -178,6 +194,9 @@ def load(path: str = LIB_PATH):
     lib.gwc_server_stats.restype = c_int
     lib.gwc_server_destroy.argtypes = [c_void_p]
     lib.gwc_server_destroy.restype = c_int
+    lib.gwc_sigma_analytic.argtypes = [POINTER(GwcSystem), POINTER(GwcAnalyticArgs),
+                                       POINTER(GwcAnalyticOut), c_void_p]
+    lib.gwc_sigma_analytic.restype = c_int
     lib.gwc_probe_peak.argtypes = [c_int, POINTER(c_double), c_void_p]
     lib.gwc_probe_peak.restype = c_int
     _lib = lib

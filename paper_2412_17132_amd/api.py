@@ -102,6 +102,40 @@ def gwc_sigma_core(eps, occ, M_oo, M_ov, core_idx, omega_imag, w_imag, omega_rea
     return out
 
 
+def gwc_sigma_analytic(eps, occ, M_oo, M_ov, core_idx, omega_real, eta, vxc=None,
+                       out: Optional[dict] = None, stream=None) -> dict:
+    """Fully analytic G0W0 Sigma^c_n(w) of the core states (gwc_sigma_analytic):
+    Casida excitations, transition moments and the pole sum of Eq. sigma_spectral.
+    Returns a dict with sigma_c [n_core][n_real][2], sigma_c_eps [n_core][2],
+    sigma_x, e_qp, a_gw and a_dh [n_core][n_real], omega_exc [n_occ n_virt]
+    (ascending) and sweeps [1] (int32)."""
+    lib = N.load()
+    n_aux, n_occ, n_virt = (int(s) for s in M_ov.shape)
+    n_core = int(core_idx.shape[0])
+    n_real = int(omega_real.shape[-1])
+    keep: list = []
+    sys = N.GwcSystem(n_aux, n_occ, n_virt, _as_arg(eps, "f8", keep), _as_arg(occ, "f8", keep),
+                      _as_arg(M_oo, "f8", keep), _as_arg(M_ov, "f8", keep))
+    args = N.GwcAnalyticArgs(n_core, _as_arg(core_idx, "i4", keep), n_real,
+                             _as_arg(omega_real, "f8", keep), float(eta), _as_arg(vxc, "f8", keep))
+    if out is None:
+        out = {
+            "sigma_c": _alloc((n_core, n_real, 2), M_ov),
+            "sigma_c_eps": _alloc((n_core, 2), M_ov),
+            "sigma_x": _alloc((n_core,), M_ov),
+            "e_qp": _alloc((n_core,), M_ov),
+            "a_gw": _alloc((n_core, n_real), M_ov),
+            "a_dh": _alloc((n_core, n_real), M_ov),
+            "omega_exc": _alloc((n_occ * n_virt,), M_ov),
+            "sweeps": np.zeros(1, dtype=np.int32),
+        }
+    o = N.GwcAnalyticOut(*(_as_out(out.get(k)) for k in
+                           ("sigma_c", "sigma_c_eps", "sigma_x", "e_qp", "a_gw", "a_dh",
+                            "omega_exc", "sweeps")))
+    N.check(lib.gwc_sigma_analytic(sys, args, o, _stream_handle(stream)))
+    return out
+
+
 def wac_paper_settings(n_core_pts: int = 100, n_val_pts: int = 100) -> dict:
     """The paper's CD-WAC settings (section "Computational Details"): 100 core-window
     and 100 valence-window points, core window 0..40 eV, valence margins 8 % below

@@ -69,8 +69,9 @@ struct PendingTiming {
   hipEvent_t a, b;
   double flops;
 };
-constexpr int kNumTimed = 3;
-const char *const kTimedKernels[kNumTimed] = {"pi_build_f64", "lu_bordered", "pi_build_mixed"};
+constexpr int kNumTimed = 5;
+const char *const kTimedKernels[kNumTimed] = {"pi_build_f64", "lu_bordered", "pi_build_mixed",
+                                              "jacobi_apply", "jacobi_pairs"};
 std::mutex g_timing_mutex;
 std::atomic<bool> g_timing{false};
 TimerStat g_stats[kNumTimed];
@@ -975,6 +976,149 @@ void run_cumulant(const gwc_cumulant_args *a, double *A_out, double *z_out, hipS
   HIPCHECK(hipStreamSynchronize(s));
 }
 
+// Fully analytic G0W0 (kernels_analytic.hip): Casida matrix, block-Jacobi
+// eigensolver with the rotations carried into Y = Delta^1/2 L, transition
+// moments, pole sums, E_QP and the spectral functions.
+struct AnalyticInputs {
+  std::vector<int> core;
+  std::vector<double> wr, vxc;
+};
+
+// Host-side checks of gwc_sigma_analytic's arguments (no device work).
+AnalyticInputs check_analytic_args(int n_occ, long long n_ov, const gwc_analytic_args *args,
+                                   const gwc_analytic_out *out, hipStream_t s) {
+  if (!args || !out) fail(GWC_ERR_INVALID_ARG, "NULL args or out");
+  if (!out->sigma_c) fail(GWC_ERR_INVALID_ARG, "sigma_c is required");
+  const int nc = args->n_core, nr = args->n_real;
+  if (nc < 1 || nr < 1) fail(GWC_ERR_SHAPE, "n_core, n_real must be >= 1");
+  if (!args->core_idx || !args->omega_real) fail(GWC_ERR_INVALID_ARG, "NULL input array");
+  if (!std::isfinite(args->eta)) fail(GWC_ERR_NONFINITE, "non-finite eta");
+  if (!(args->eta > 0.0)) fail(GWC_ERR_INVALID_ARG, "eta must be > 0");
+  if (n_ov > 65536) fail(GWC_ERR_SHAPE, "n_occ * n_virt = %lld exceeds 65536", n_ov);
+  AnalyticInputs in;
+  in.core = to_host(args->core_idx, nc, s);
+  in.wr = to_host(args->omega_real, (size_t)nc * nr, s);
+  in.vxc.assign(nc, 0.0);
+  if (args->vxc) in.vxc = to_host(args->vxc, nc, s);
+  if (!all_finite(in.wr) || !all_finite(in.vxc)) fail(GWC_ERR_NONFINITE, "non-finite value in omega_real or vxc");
+  for (int c = 0; c < nc; ++c) {
+    if (in.core[c] < 0 || in.core[c] >= n_occ) fail(GWC_ERR_SHAPE, "core_idx[%d] = %d not in [0, n_occ)", c, in.core[c]);
+    for (int j = 1; j < nr; ++j)
+      if (!(in.wr[(size_t)c * nr + j] > in.wr[(size_t)c * nr + j - 1]))
+        fail(GWC_ERR_INVALID_ARG, "omega_real of core %d must increase", c);
+  }
+  return in;
+}
+
+void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analytic_out *out,
+                  hipStream_t s) {
+  const AnalyticInputs in = check_analytic_args(rs.no, rs.n_ov, args, out, s);
+  const std::vector<int> &core = in.core;
+  const std::vector<double> &wr = in.wr, &vxc = in.vxc;
+  const int nc = args->n_core, nr = args->n_real;
+  const int N = rs.N, no = rs.no, nv = rs.nv, nbas = rs.nb, n = rs.n_ov;
+  const int JB2 = 2 * jacobi_block();
+  const int n_pad = (int)round_up(n, JB2), nblk = n_pad / jacobi_block(), np = nblk / 2;
+  const long long ld = n_pad;
+
+  DevBuf dcore(s), dwr(s), dvxc(s), dC(s), dVt(s), dY(s), dVp(s), drot(s), dOm(s), dsort(s);
+  const int *d_core = upload(dcore, core, s);
+  const double *d_wr = upload(dwr, wr, s);
+  const double *d_vxc = upload(dvxc, vxc, s);
+  dC.alloc((size_t)n_pad * n_pad * sizeof(double));
+  dVt.alloc((size_t)N * n_pad * sizeof(double));
+  dY.alloc((size_t)N * n_pad * sizeof(double));
+  dVp.alloc((size_t)np * JB2 * JB2 * sizeof(double));
+  drot.alloc(sizeof(int));
+  dOm.alloc((size_t)n_pad * sizeof(double));
+  dsort.alloc((size_t)n * sizeof(double));
+  double *C = dC.as<double>(), *Y = dY.as<double>();
+
+  // C = Vt^T Vt + diag(Delta^2) over the padded order (the padding stays zero)
+  launch_casida_operands(rs.d_Mov.as<double>(), rs.d_eps.as<double>(), N, no, nv, n_pad,
+                         dVt.as<double>(), Y, s);
+  launch_gemm_tn(dVt.as<double>(), ld, dVt.as<double>(), ld, n_pad, n_pad, N, C, ld,
+                 rs.d_eps.as<double>(), no, nv, n, s);
+  HIPCHECK(hipGetLastError());
+  dVt.release();
+
+  std::vector<PendingTiming> pending;
+  const bool timing = g_timing;
+  const double tol = 1e-14;
+  const int ytiles = (N + JB2 - 1) / JB2;
+  const double fl_apply = (double)np * (np + 1) / 2 * 4.0 * JB2 * JB2 * JB2 +
+                          (double)ytiles * np * 2.0 * JB2 * JB2 * JB2;
+  const double fl_pairs = (double)np * (JB2 - 1) * 18.0 * jacobi_block() * JB2;
+  int sweeps = 0, rot = 1;
+  constexpr int kMaxSweeps = 60;
+  while (rot != 0) {
+    if (sweeps == kMaxSweeps) fail(GWC_ERR_FACTORIZATION, "block Jacobi not converged after %d sweeps", kMaxSweeps);
+    launch_zero_counter(drot.as<int>(), s);
+    for (int r = 0; r < nblk - 1; ++r) {
+      hipEvent_t ea = timing ? timing_mark(s) : nullptr;
+      launch_jacobi_pairs(C, ld, nblk, r, tol, dVp.as<double>(), drot.as<int>(), s);
+      hipEvent_t eb = timing ? timing_mark(s) : nullptr;
+      hipEvent_t ec = timing ? timing_mark(s) : nullptr;
+      launch_jacobi_apply(C, ld, nblk, r, dVp.as<double>(), Y, ld, N, s);
+      if (timing) {
+        pending.push_back({4, ea, eb, fl_pairs});
+        pending.push_back({3, ec, timing_mark(s), fl_apply});
+      }
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(&rot, drot.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    ++sweeps;
+    timing_resolve(pending);
+  }
+
+  launch_excitations(C, ld, n, n_pad, dOm.as<double>(), dsort.as<double>(), s);
+  {
+    DevBuf dflag(s);
+    dflag.alloc(sizeof(int));
+    HIPCHECK(hipMemsetAsync(dflag.p, 0, sizeof(int), s));
+    launch_nonfinite(dOm.as<double>(), n_pad, dflag.as<int>(), s);
+    int flag = 0;
+    HIPCHECK(hipMemcpyAsync(&flag, dflag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (flag) fail(GWC_ERR_FACTORIZATION, "non-positive eigenvalue of the Casida matrix");
+  }
+  dC.release();
+
+  // Q[c nb + m][nu] = sum_P M^P_{n_c m} R[P][nu], R = Y after the rotations
+  DevBuf dBp(s), dQ(s), dpart(s), dsig(s), dsx(s), dsc(s), dse(s), deq(s), dagw(s), dadh(s);
+  const int cols = nc * nbas, npts = nr + 1;
+  dBp.alloc((size_t)N * cols * sizeof(double));
+  dQ.alloc((size_t)cols * n * sizeof(double));
+  launch_pack_pairs(rs.d_Moo.as<double>(), rs.d_Mov.as<double>(), N, no, nv, d_core, nc,
+                    dBp.as<double>(), s);
+  launch_gemm_tn(dBp.as<double>(), cols, Y, ld, cols, n, N, dQ.as<double>(), n, nullptr, 0, 1, 0, s);
+  dpart.alloc((size_t)pole_sum_blocks(n) * nc * npts * sizeof(double2));
+  dsig.alloc((size_t)nc * npts * sizeof(double2));
+  launch_pole_sum(dQ.as<double>(), n, dOm.as<double>(), n, rs.d_eps.as<double>(), no, nbas, d_core,
+                  nc, d_wr, nr, args->eta, dpart.as<double2>(), dsig.as<double2>(), s);
+  dsx.alloc(nc * sizeof(double));
+  launch_sigma_x(rs.d_Moo.as<double>(), N, no, d_core, nc, dsx.as<double>(), s);
+  dsc.alloc((size_t)nc * nr * 2 * sizeof(double));
+  dse.alloc((size_t)nc * 2 * sizeof(double));
+  deq.alloc(nc * sizeof(double));
+  dagw.alloc((size_t)nc * nr * sizeof(double));
+  dadh.alloc((size_t)nc * nr * sizeof(double));
+  launch_analytic_finish(dsig.as<double2>(), nc, nr, rs.d_eps.as<double>(), d_core, d_wr,
+                         dsx.as<double>(), d_vxc, dsc.as<double>(), dse.as<double>(),
+                         deq.as<double>(), dagw.as<double>(), dadh.as<double>(), s);
+  HIPCHECK(hipGetLastError());
+  copy_out(out->sigma_c, dsc.p, (size_t)nc * nr * 2 * sizeof(double), s);
+  copy_out(out->sigma_c_eps, dse.p, (size_t)nc * 2 * sizeof(double), s);
+  copy_out(out->sigma_x, dsx.p, (size_t)nc * sizeof(double), s);
+  copy_out(out->e_qp, deq.p, (size_t)nc * sizeof(double), s);
+  copy_out(out->a_gw, dagw.p, (size_t)nc * nr * sizeof(double), s);
+  copy_out(out->a_dh, dadh.p, (size_t)nc * nr * sizeof(double), s);
+  copy_out(out->omega_exc, dsort.p, (size_t)n * sizeof(double), s);
+  if (out->sweeps) copy_out(out->sweeps, &sweeps, sizeof(int32_t), s);
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
 }  // namespace gwc
 
 namespace {
@@ -1048,6 +1192,19 @@ int gwc_sigma_core_resident(gwc_system_handle handle, const gwc_sigma_args *args
   return guarded([&] {
     if (!handle || !args || !out) fail(GWC_ERR_INVALID_ARG, "NULL handle, args or out");
     gwc::run_sigma(*handle->rs, args, out, (hipStream_t)hip_stream, 0);
+    return GWC_OK;
+  });
+}
+
+int gwc_sigma_analytic(const gwc_system *sys, const gwc_analytic_args *args, gwc_analytic_out *out,
+                       void *hip_stream) {
+  return guarded([&] {
+    if (!sys || !args || !out) fail(GWC_ERR_INVALID_ARG, "NULL system, args or out");
+    hipStream_t s = (hipStream_t)hip_stream;
+    // argument checks that need no device come first
+    (void)gwc::check_analytic_args(sys->n_occ, (long long)sys->n_occ * sys->n_virt, args, out, s);
+    std::unique_ptr<gwc::ResidentSystem> rs(gwc::create_resident(sys, s));
+    gwc::run_analytic(*rs, args, out, s);
     return GWC_OK;
   });
 }

@@ -102,4 +102,36 @@ void launch_pade_eval(const double2 *z_task, const int *pair_of_task, const int4
                       const long long *node_off, const double2 *node_z, const double2 *coef,
                       int T, double2 *W_out, hipStream_t stream);
 
+// Fully analytic G0W0 (kernels_analytic.hip).  Casida matrix C (n_pad x n_pad,
+// ld n_pad) and Y = Delta^1/2 L (n_aux x n_pad) are zero-padded to n_pad, a
+// multiple of 2 jacobi_block().
+int jacobi_block();
+void launch_casida_operands(const double *M_ov, const double *eps, int n_aux, int n_occ, int n_virt,
+                            int ld, double *Vt, double *Y, hipStream_t s);
+// out[i][j] = sum_k A[k][i] B[k][j] (+ Delta_i^2 for i == j < n_diag when eps != NULL).
+void launch_gemm_tn(const double *A, long long lda, const double *B, long long ldb, int M, int N,
+                    int K, double *out, long long ldo, const double *eps, int n_occ, int n_virt,
+                    int n_diag, hipStream_t s);
+void launch_zero_counter(int *x, hipStream_t s);
+// One round r of a block-Jacobi sweep over nb blocks: pair rotations V stored as
+// Ep = V - I (nb/2 x 64 x 64), counted in *rotations; then C <- V^T C V and Y <- Y V.
+void launch_jacobi_pairs(const double *C, long long ldc, int nb, int r, double tol, double *Ep,
+                         int *rotations, hipStream_t s);
+void launch_jacobi_apply(double *C, long long ldc, int nb, int r, const double *Ep, double *Y,
+                         long long ldy, int n_aux, hipStream_t s);
+// Om[nu] = sqrt(C[nu][nu]) (nu < n; 1 on the padding); sorted (may be NULL) ascending.
+void launch_excitations(const double *C, long long ldc, int n, int n_pad, double *Om,
+                        double *sorted, hipStream_t s);
+void launch_pack_pairs(const double *M_oo, const double *M_ov, int n_aux, int n_occ, int n_virt,
+                       const int *core, int n_core, double *Bp, hipStream_t s);
+// part holds pole_sum_blocks(n_ov) x n_core x (n_real + 1) double2.
+int pole_sum_blocks(int n_ov);
+void launch_pole_sum(const double *Q, long long ldq, const double *Om, int n_ov, const double *eps,
+                     int n_occ, int n_basis, const int *core, int n_core, const double *omega_real,
+                     int n_real, double eta, double2 *part, double2 *sigma, hipStream_t s);
+void launch_analytic_finish(const double2 *sigma, int n_core, int n_real, const double *eps,
+                            const int *core, const double *omega_real, const double *sigma_x,
+                            const double *vxc, double *sigma_c, double *sigma_c_eps, double *e_qp,
+                            double *a_gw, double *a_dh, hipStream_t s);
+
 }  // namespace gwc

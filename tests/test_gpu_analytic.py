@@ -1,0 +1,111 @@
+"""GPU parity of the fully analytic G0W0 path (gwc_sigma_analytic) against the
+analytic oracle: the Casida excitations, Sigma^c of Eq. sigma_spectral, E_QP
+and the G0W0 / G_DH W0 spectral functions.
+
+Bar: 1e-9 relative to each output's largest magnitude, as for contour
+deformation.  The GPU eigensolver (block Jacobi) and the oracle's LAPACK
+eigensolver differ by rounding: both are backward stable, so Omega agrees to
+~1e-13 relative and Sigma^c, a smooth function of C at distance eta from its
+poles, to ~1e-11.  Individual eigenvectors are not compared (near-degenerate
+excitations mix freely); every output here is invariant under that mixing."""
+import numpy as np
+import pytest
+
+import paper_2412_17132_amd as gwc
+from oracle import analytic as AN
+from workloads import CONFIGS, system_from_config
+from workloads.configs import small_config
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+TOL = 1e-9
+
+CASES = [
+    # n_occ, n_virt, n_aux, n_core, n_real, seed: n_ov = 15 (one block pair), 92, 205
+    # (ragged against the 64-wide pair blocks), 279 with 3 cores
+    (3, 5, 12, 1, 9, 11),
+    (4, 23, 50, 2, 17, 5),
+    (5, 41, 90, 1, 33, 7),
+    (9, 31, 120, 3, 70, 13),
+]
+
+
+def _cplx(a):
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def _gpu(s, omega_real=None, vxc=None):
+    d = gwc.to_device(s, torch.device("cuda:0"))
+    om = d["omega_real"] if omega_real is None else torch.as_tensor(omega_real, device="cuda:0")
+    out = gwc.gwc_sigma_analytic(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"], om,
+                                 d["eta"], vxc=vxc)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
+
+
+def _compare(out, ref):
+    # eigenvalues lambda = Omega^2 of C: both eigensolvers are backward stable, so
+    # |d lambda| = O(eps ||C||) in absolute terms (1e-12 lambda_max leaves a factor
+    # ~4500 over eps for the accumulated rounding)
+    lam, lam_ref = out["omega_exc"] ** 2, ref["omega_exc"] ** 2
+    dl = np.max(np.abs(lam - lam_ref)) / lam_ref.max()
+    rel = {k: np.max(np.abs(a - b)) / np.max(np.abs(b)) for k, a, b in (
+        ("sigma_c", _cplx(out["sigma_c"]), ref["sigma_c"]),
+        ("sigma_c_eps", _cplx(out["sigma_c_eps"]), ref["sigma_c_eps"]),
+        ("e_qp", out["e_qp"], ref["e_qp"]), ("a_gw", out["a_gw"], ref["a_gw"]),
+        ("a_dh", out["a_dh"], ref["a_dh"]))}
+    print(f"  lambda err / lambda_max {dl:.2e}; " +
+          ", ".join(f"{k} {v:.2e}" for k, v in rel.items()), flush=True)
+    assert dl <= 1e-12
+    assert np.allclose(out["sigma_x"], ref["sigma_x"], rtol=1e-13, atol=0)
+    for k, v in rel.items():
+        assert v <= TOL, (k, v)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"ov{c[0] * c[1]}_core{c[3]}" for c in CASES])
+def test_analytic_parity(case):
+    n_occ, n_virt, n_aux, n_core, n_real, seed = case
+    s = system_from_config(small_config(n_occ=n_occ, n_virt=n_virt, n_aux=n_aux, n_core=n_core,
+                                        n_real=n_real, seed=seed))
+    print(f"case analytic {case}", flush=True)
+    out = _gpu(s)
+    ref = AN.sigma_analytic_system(s)
+    _compare(out, ref)
+    assert 1 <= int(out["sweeps"][0]) < 60
+
+
+def test_analytic_c1_with_vxc():
+    s = system_from_config(CONFIGS["c1"])
+    vxc = np.array([-0.37])
+    print("case analytic c1 vxc", flush=True)
+    out = _gpu(s, vxc=torch.as_tensor(vxc, device="cuda:0"))
+    ref = AN.sigma_analytic_system(s, vxc=vxc)
+    _compare(out, ref)
+
+
+def test_analytic_c2_sampled():
+    """Benzene-sized system (N_ov = 5859, 6 cores) at the size the bench times:
+    every excitation energy, and Sigma^c / E_QP / A at 6 points per core."""
+    s = system_from_config(CONFIGS["c2"])
+    idx = np.linspace(0, s.omega_real.shape[1] - 1, 6).astype(int)
+    om = np.ascontiguousarray(s.omega_real[:, idx])
+    print("case analytic c2 sampled", flush=True)
+    out = _gpu(s, omega_real=om)
+    ref = AN.sigma_analytic(s.eps, s.occ, s.M_oo, s.M_ov, s.core_idx, om, s.eta)
+    _compare(out, ref)
+
+
+def test_analytic_matches_cd_quasiparticle_energy():
+    """The analytic and the contour-deformation GPU paths give the same E_QP for
+    a converged imaginary grid and small eta (two independent GPU routes)."""
+    from workloads import mgl_grid
+    s = system_from_config(small_config(n_occ=4, n_virt=12, n_aux=30, n_core=2, n_real=5, seed=9))
+    x, w = mgl_grid(200, 0.5)
+    s.omega_imag, s.w_imag, s.eta = x, w, 1e-7
+    print("case analytic vs cd", flush=True)
+    an = _gpu(s)
+    d = gwc.to_device(s, torch.device("cuda:0"))
+    cd = gwc.gwc_sigma_core(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"], d["omega_imag"],
+                            d["w_imag"], d["omega_real"], d["eta"])
+    torch.cuda.synchronize()
+    assert np.allclose(an["e_qp"], cd["e_qp"].cpu().numpy(), rtol=1e-9, atol=0)

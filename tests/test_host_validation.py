@@ -134,3 +134,29 @@ def test_qp_newton_argument_errors(gwc):
     with pytest.raises(gwc.GwcError) as ei:
         _call(gwc, s, qp=dict(max_iter=5, tol=1e-8, step=1e-4), wac=OW.paper_params())
     assert ei.value.status == -8
+
+
+@pytest.mark.parametrize("case,status", [
+    ("gap", -3), ("core", -2), ("eta", -1), ("grid_order", -1), ("nan_grid", -4), ("big", -2),
+])
+def test_sigma_analytic_argument_errors(gwc, case, status):
+    s = _sys()
+    kw = dict(eps=s.eps, occ=s.occ, M_oo=s.M_oo, M_ov=s.M_ov, core_idx=s.core_idx,
+              omega_real=s.omega_real, eta=s.eta)
+    if case == "gap":
+        s.eps[2] = s.eps[3] + 0.01
+    elif case == "core":
+        kw["core_idx"] = np.array([3], dtype=np.int32)
+    elif case == "eta":
+        kw["eta"] = -1.0
+    elif case == "grid_order":
+        s.omega_real[0, 2] = s.omega_real[0, 1]
+    elif case == "nan_grid":
+        s.omega_real[0, 0] = np.inf
+    elif case == "big":
+        # n_occ * n_virt = 3 * 21846 > 65536: refused before any array is read
+        kw["M_ov"] = np.lib.stride_tricks.as_strided(np.zeros(1), shape=(8, 3, 21846),
+                                                     strides=(0, 0, 0))
+    with pytest.raises(gwc.GwcError) as ei:
+        gwc.gwc_sigma_analytic(**kw)
+    assert ei.value.status == status, str(ei.value)
