@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "core-state Σc(ω) solves/sec + Π-build MFMA util; p50/p99 latency, mixed vs FP64"
 FP64_MFMA_PEAK_TFLOPS = 78.6
+# FP64 vector (FMA) peak: 256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 # dense MFMA peaks of the mixed forms (TFLOP/s): 16-bit 2.5 P, fp8 5.0 P
 MIXED_MFMA_PEAK_TFLOPS = {"bf16x3": 2500.0, "fp16x3": 2500.0, "fp8": 5000.0}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pi_build_f64_c2_traffic.json")
@@ -389,6 +391,8 @@ def main():
                     help="skip the CD-WAC leg (the paper's settings) reported beside the CD value")
     ap.add_argument("--no-decoupled", action="store_true",
                     help="skip the DECOUPLED-mode leg reported beside the FULL value")
+    ap.add_argument("--no-analytic", action="store_true",
+                    help="skip the fully analytic G0W0 leg (Casida eigensolve + pole sums)")
     ap.add_argument("--sample-points", type=int, default=0,
                     help="sampled run for large workloads (c3, c4): one core state at 1 and this "
                          "many real points, extrapolated to the full grid")
@@ -623,6 +627,36 @@ def main():
             "residue_tasks_per_step": residue_task_count(s.eps, s.occ, s.core_idx, s.omega_real,
                                                              "decoupled"),
             "precision": args.precision,
+        }
+    if args.mode == "full" and not args.no_analytic:
+        def astep():
+            return gwc.gwc_sigma_analytic(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],
+                                          d["omega_real"], d["eta"])
+        astep()  # warm-up
+        torch.cuda.synchronize()
+        gwc.timing_enable(True)
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            aout = astep()
+        torch.cuda.synchronize()
+        el_a = time.perf_counter() - ta
+        ja, jp = gwc.timing_get("jacobi_apply"), gwc.timing_get("jacobi_pairs")
+        gwc.timing_enable(False)
+        ja_tf = ja["flops"] / (ja["total_ms"] / 1e3) / 1e12 if ja["total_ms"] > 0 else 0.0
+        ref_out = last[0]
+        deq = np.abs(aout["e_qp"].cpu().numpy() - ref_out["e_qp"].cpu().numpy())
+        res["analytic"] = {
+            "value": solves / el_a, "unit": "solves/s", "ms_per_step": el_a / args.steps * 1e3,
+            "speedup_vs_cd": elapsed / el_a,
+            "n_ov": int(s.M_ov.shape[1] * s.M_ov.shape[2]),
+            "jacobi_sweeps": int(aout["sweeps"][0]),
+            "jacobi_apply": {"ms_per_step": ja["total_ms"] / args.steps,
+                             "launches_per_step": ja["launches"] / args.steps,
+                             "avg_launch_ms": ja["total_ms"] / max(ja["launches"], 1),
+                             "bound": "alu", "achieved": ja_tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": ja_tf / FP64_VECTOR_PEAK_TFLOPS},
+            "jacobi_pairs_ms_per_step": jp["total_ms"] / args.steps,
+            "e_qp_dev_from_cd_mev": float(deq.max() * EV_PER_HA * 1e3),
         }
     if not args.no_peaks:
         pk = measure_peaks(gwc)

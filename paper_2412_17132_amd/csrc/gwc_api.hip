@@ -1021,7 +1021,7 @@ void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analyti
   const int n_pad = (int)round_up(n, JB2), nblk = n_pad / jacobi_block(), np = nblk / 2;
   const long long ld = n_pad;
 
-  DevBuf dcore(s), dwr(s), dvxc(s), dC(s), dVt(s), dY(s), dVp(s), drot(s), dOm(s), dsort(s);
+  DevBuf dcore(s), dwr(s), dvxc(s), dC(s), dVt(s), dY(s), dVp(s), dact(s), drot(s), dOm(s), dsort(s);
   const int *d_core = upload(dcore, core, s);
   const double *d_wr = upload(dwr, wr, s);
   const double *d_vxc = upload(dvxc, vxc, s);
@@ -1029,46 +1029,59 @@ void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analyti
   dVt.alloc((size_t)N * n_pad * sizeof(double));
   dY.alloc((size_t)N * n_pad * sizeof(double));
   dVp.alloc((size_t)np * JB2 * JB2 * sizeof(double));
-  drot.alloc(sizeof(int));
+  dact.alloc((size_t)np * sizeof(int));
+  drot.alloc(3 * sizeof(int));  // rotations, C tiles and Y tiles updated in a sweep
   dOm.alloc((size_t)n_pad * sizeof(double));
   dsort.alloc((size_t)n * sizeof(double));
   double *C = dC.as<double>(), *Y = dY.as<double>();
 
+  // transitions ordered by Delta, so that near-degenerate ones share Jacobi blocks
+  std::vector<int> perm(n);
+  std::vector<double> delta(n), diag2(n);
+  for (int i = 0; i < no; ++i)
+    for (int a = 0; a < nv; ++a) delta[(size_t)i * nv + a] = rs.eps[no + a] - rs.eps[i];
+  for (int k = 0; k < n; ++k) perm[k] = k;
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return delta[x] < delta[y]; });
+  for (int k = 0; k < n; ++k) diag2[k] = delta[perm[k]] * delta[perm[k]];
+  DevBuf dperm(s), ddiag(s);
+  const int *d_perm = upload(dperm, perm, s);
+  const double *d_diag2 = upload(ddiag, diag2, s);
   // C = Vt^T Vt + diag(Delta^2) over the padded order (the padding stays zero)
-  launch_casida_operands(rs.d_Mov.as<double>(), rs.d_eps.as<double>(), N, no, nv, n_pad,
+  launch_casida_operands(rs.d_Mov.as<double>(), rs.d_eps.as<double>(), d_perm, N, no, nv, n_pad,
                          dVt.as<double>(), Y, s);
-  launch_gemm_tn(dVt.as<double>(), ld, dVt.as<double>(), ld, n_pad, n_pad, N, C, ld,
-                 rs.d_eps.as<double>(), no, nv, n, s);
+  launch_gemm_tn(dVt.as<double>(), ld, dVt.as<double>(), ld, n_pad, n_pad, N, C, ld, d_diag2, n, s);
   HIPCHECK(hipGetLastError());
   dVt.release();
 
   std::vector<PendingTiming> pending;
   const bool timing = g_timing;
   const double tol = 1e-14;
-  const int ytiles = (N + JB2 - 1) / JB2;
-  const double fl_apply = (double)np * (np + 1) / 2 * 4.0 * JB2 * JB2 * JB2 +
-                          (double)ytiles * np * 2.0 * JB2 * JB2 * JB2;
+  // flops of one updated tile: C tiles two 64^3 products, Y tiles one
+  const double fl_ctile = 4.0 * JB2 * JB2 * JB2, fl_ytile = 2.0 * JB2 * JB2 * JB2;
   const double fl_pairs = (double)np * (JB2 - 1) * 18.0 * jacobi_block() * JB2;
-  int sweeps = 0, rot = 1;
+  int sweeps = 0, counts[3] = {1, 0, 0};
   constexpr int kMaxSweeps = 60;
-  while (rot != 0) {
+  while (counts[0] != 0) {
     if (sweeps == kMaxSweeps) fail(GWC_ERR_FACTORIZATION, "block Jacobi not converged after %d sweeps", kMaxSweeps);
-    launch_zero_counter(drot.as<int>(), s);
+    launch_zero_counters(drot.as<int>(), 3, s);
     for (int r = 0; r < nblk - 1; ++r) {
       hipEvent_t ea = timing ? timing_mark(s) : nullptr;
-      launch_jacobi_pairs(C, ld, nblk, r, tol, dVp.as<double>(), drot.as<int>(), s);
+      launch_jacobi_pairs(C, ld, nblk, r, tol, dVp.as<double>(), dact.as<int>(), drot.as<int>(), s);
       hipEvent_t eb = timing ? timing_mark(s) : nullptr;
       hipEvent_t ec = timing ? timing_mark(s) : nullptr;
-      launch_jacobi_apply(C, ld, nblk, r, dVp.as<double>(), Y, ld, N, s);
+      launch_jacobi_apply(C, ld, nblk, r, dVp.as<double>(), dact.as<int>(), Y, ld, N,
+                          drot.as<int>() + 1, s);
       if (timing) {
         pending.push_back({4, ea, eb, fl_pairs});
-        pending.push_back({3, ec, timing_mark(s), fl_apply});
+        pending.push_back({3, ec, timing_mark(s), 0.0});
       }
     }
     HIPCHECK(hipGetLastError());
-    HIPCHECK(hipMemcpyAsync(&rot, drot.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(counts, drot.p, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     ++sweeps;
+    // the sweep's executed tile flops, booked on its last apply launch
+    if (timing) pending.back().flops = counts[1] * fl_ctile + counts[2] * fl_ytile;
     timing_resolve(pending);
   }
 
@@ -1092,7 +1105,7 @@ void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analyti
   dQ.alloc((size_t)cols * n * sizeof(double));
   launch_pack_pairs(rs.d_Moo.as<double>(), rs.d_Mov.as<double>(), N, no, nv, d_core, nc,
                     dBp.as<double>(), s);
-  launch_gemm_tn(dBp.as<double>(), cols, Y, ld, cols, n, N, dQ.as<double>(), n, nullptr, 0, 1, 0, s);
+  launch_gemm_tn(dBp.as<double>(), cols, Y, ld, cols, n, N, dQ.as<double>(), n, nullptr, 0, s);
   dpart.alloc((size_t)pole_sum_blocks(n) * nc * npts * sizeof(double2));
   dsig.alloc((size_t)nc * npts * sizeof(double2));
   launch_pole_sum(dQ.as<double>(), n, dOm.as<double>(), n, rs.d_eps.as<double>(), no, nbas, d_core,

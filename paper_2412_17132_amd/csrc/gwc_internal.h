@@ -106,19 +106,23 @@ void launch_pade_eval(const double2 *z_task, const int *pair_of_task, const int4
 // ld n_pad) and Y = Delta^1/2 L (n_aux x n_pad) are zero-padded to n_pad, a
 // multiple of 2 jacobi_block().
 int jacobi_block();
-void launch_casida_operands(const double *M_ov, const double *eps, int n_aux, int n_occ, int n_virt,
-                            int ld, double *Vt, double *Y, hipStream_t s);
-// out[i][j] = sum_k A[k][i] B[k][j] (+ Delta_i^2 for i == j < n_diag when eps != NULL).
+// Transition-space column k holds ia = perm[k] (a permutation of [0, n_occ n_virt)).
+void launch_casida_operands(const double *M_ov, const double *eps, const int *perm, int n_aux,
+                            int n_occ, int n_virt, int ld, double *Vt, double *Y, hipStream_t s);
+// out[i][j] = sum_k A[k][i] B[k][j] (+ diag[i] for i == j < n_diag when diag != NULL).
 void launch_gemm_tn(const double *A, long long lda, const double *B, long long ldb, int M, int N,
-                    int K, double *out, long long ldo, const double *eps, int n_occ, int n_virt,
-                    int n_diag, hipStream_t s);
-void launch_zero_counter(int *x, hipStream_t s);
+                    int K, double *out, long long ldo, const double *diag, int n_diag,
+                    hipStream_t s);
+void launch_zero_counters(int *x, int n, hipStream_t s);  // n <= 64
 // One round r of a block-Jacobi sweep over nb blocks: pair rotations V stored as
-// Ep = V - I (nb/2 x 64 x 64), counted in *rotations; then C <- V^T C V and Y <- Y V.
+// Ep = V - I (nb/2 x 64 x 64), active[nb/2] flags pairs that rotated, counted in
+// *rotations; then C <- V^T C V and Y <- Y V, adding the 64 x 64 C and Y tiles
+// it updated to work[0] and work[1].
 void launch_jacobi_pairs(const double *C, long long ldc, int nb, int r, double tol, double *Ep,
-                         int *rotations, hipStream_t s);
-void launch_jacobi_apply(double *C, long long ldc, int nb, int r, const double *Ep, double *Y,
-                         long long ldy, int n_aux, hipStream_t s);
+                         int *active, int *rotations, hipStream_t s);
+void launch_jacobi_apply(double *C, long long ldc, int nb, int r, const double *Ep,
+                         const int *active, double *Y, long long ldy, int n_aux, int *work,
+                         hipStream_t s);
 // Om[nu] = sqrt(C[nu][nu]) (nu < n; 1 on the padding); sorted (may be NULL) ascending.
 void launch_excitations(const double *C, long long ldc, int n, int n_pad, double *Om,
                         double *sorted, hipStream_t s);

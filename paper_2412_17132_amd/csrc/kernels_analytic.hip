@@ -49,19 +49,21 @@ __device__ __forceinline__ int pair_index(int2 IJ, int t) {
 
 }  // namespace
 
-// Vt[P][ia] = 2 sqrt(Delta_ia) M^P_ia and Y[P][ia] = sqrt(Delta_ia) M^P_ia for
-// ia < n_ov, zero for n_ov <= ia < ld (the padding).
+// Column k of the (permuted) transition space is ia = perm[k]:
+// Vt[P][k] = 2 sqrt(Delta_ia) M^P_ia and Y[P][k] = sqrt(Delta_ia) M^P_ia for
+// k < n_ov, zero for n_ov <= k < ld (the padding).
 __global__ void __launch_bounds__(256)
-casida_operands_kernel(const double *__restrict__ M_ov, const double *__restrict__ eps, int n_aux,
-                       int n_occ, int n_virt, int ld, double *__restrict__ Vt,
-                       double *__restrict__ Y) {
+casida_operands_kernel(const double *__restrict__ M_ov, const double *__restrict__ eps,
+                       const int *__restrict__ perm, int n_aux, int n_occ, int n_virt, int ld,
+                       double *__restrict__ Vt, double *__restrict__ Y) {
   const long long total = (long long)n_aux * ld;
   const int n_ov = n_occ * n_virt;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
-    const int P = (int)(e / ld), ia = (int)(e % ld);
+    const int P = (int)(e / ld), k = (int)(e % ld);
     double v = 0.0, y = 0.0;
-    if (ia < n_ov) {
+    if (k < n_ov) {
+      const int ia = perm[k];
       const int i = ia / n_virt, a = ia % n_virt;
       const double sd = sqrt(eps[n_occ + a] - eps[i]);
       const double m = M_ov[(long long)P * n_ov + ia];
@@ -73,13 +75,13 @@ casida_operands_kernel(const double *__restrict__ M_ov, const double *__restrict
   }
 }
 
-// out[i][j] = sum_k A[k][i] B[k][j] (+ Delta_i^2 on the diagonal for i < n_diag
-// when eps != NULL), i < M, j < N.  64 x 64 tiles, K in chunks of 16 through
+// out[i][j] = sum_k A[k][i] B[k][j] (+ diag[i] on the diagonal for i < n_diag
+// when diag != NULL), i < M, j < N.  64 x 64 tiles, K in chunks of 16 through
 // LDS, 4 x 4 outputs per thread.
 __global__ void __launch_bounds__(256)
 gemm_tn_kernel(const double *__restrict__ A, long long lda, const double *__restrict__ B,
                long long ldb, int M, int N, int K, double *__restrict__ out, long long ldo,
-               const double *__restrict__ eps, int n_occ, int n_virt, int n_diag) {
+               const double *__restrict__ diag, int n_diag) {
   __shared__ double As[GK][GT + 1];
   __shared__ double Bs[GK][GT + 1];
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
@@ -116,10 +118,7 @@ gemm_tn_kernel(const double *__restrict__ A, long long lda, const double *__rest
       const int j = j0 + tx + 16 * v;
       if (j >= N) continue;
       double x = acc[u][v];
-      if (eps && i == j && i < n_diag) {
-        const double d = eps[n_occ + i % n_virt] - eps[i / n_virt];
-        x += d * d;
-      }
+      if (diag && i == j && i < n_diag) x += diag[i];
       out[(long long)i * ldo + j] = x;
     }
   }
@@ -127,14 +126,19 @@ gemm_tn_kernel(const double *__restrict__ A, long long lda, const double *__rest
 
 // One cyclic Jacobi sweep on the 64 x 64 submatrix of each block pair of round
 // r; E_out[pair] receives V - I for the accumulated rotation V (columns = new
-// basis).  E's columns p, q follow V's: with d = the identity's columns,
+// basis) and active[pair] whether any rotation was applied.  Each inner round
+// rotates 32 disjoint index pairs: every 2 x 2 block (alpha, beta) of S becomes
+// J_alpha^T S_ab J_beta with J = [[c, s], [-s, c]], and E's columns p, q follow
+// V's (d = the identity's columns):
 //   E_p <- c E_p - s E_q + (c - 1) d_p - s d_q,  E_q <- s E_p + c E_q + s d_p + (c - 1) d_q.
 __global__ void __launch_bounds__(256)
 jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, double tol,
-                   double *__restrict__ E_out, int *__restrict__ rotations) {
+                   double *__restrict__ E_out, int *__restrict__ active, int *__restrict__ rotations) {
   __shared__ double S[JP][JLD];
   __shared__ double V[JP][JLD];  // E = V - I
   __shared__ double rc[JB], rs[JB], rcm1[JB];
+  __shared__ int2 rpq[JB];
+  __shared__ int nrot_block;
   const int tid = threadIdx.x;
   const int2 IJ = circle_pair(nb, r, blockIdx.x);
   for (int e = tid; e < JP * JP; e += 256) {
@@ -142,7 +146,21 @@ jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, d
     S[a][b] = C[(long long)pair_index(IJ, a) * ldc + pair_index(IJ, b)];
     V[a][b] = 0.0;
   }
+  if (tid == 0) nrot_block = 0;
   __syncthreads();
+  // a submatrix already diagonal to the threshold needs no sweep: E = 0
+  int big = 0;
+  for (int e = tid; e < JP * JP; e += 256) {
+    const int a = e / JP, b = e % JP;
+    const double x = S[a][b];
+    big |= a < b && x != 0.0 && fabs(x) > tol * sqrt(fabs(S[a][a] * S[b][b]));
+  }
+  if (!__syncthreads_or(big)) {
+    double *Eo = E_out + (long long)blockIdx.x * JP * JP;
+    for (int e = tid; e < JP * JP; e += 256) Eo[e] = 0.0;
+    if (tid == 0) active[blockIdx.x] = 0;
+    return;
+  }
   int nrot = 0;
   for (int rr = 0; rr < JP - 1; ++rr) {
     if (tid < JB) {
@@ -161,26 +179,29 @@ jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, d
       rc[tid] = c;
       rs[tid] = s;
       rcm1[tid] = cm1;
+      rpq[tid] = pq;
     }
     __syncthreads();
-    // rows p, q of S
-    for (int e = tid; e < JB * JP; e += 256) {
-      const int k = e / JP, col = e % JP;
-      const int2 pq = circle_pair(JP, rr, k);
-      const double c = rc[k], s = rs[k];
-      const double x = S[pq.x][col], y = S[pq.y][col];
-      S[pq.x][col] = c * x - s * y;
-      S[pq.y][col] = s * x + c * y;
+    // S: 2 x 2 blocks (alpha, beta), four per thread
+    for (int e = tid; e < JB * JB; e += 256) {
+      const int al = e / JB, be = e % JB;
+      const int2 pa = rpq[al], pb = rpq[be];
+      const double ca = rc[al], sa = rs[al], cb = rc[be], sb = rs[be];
+      const double b00 = S[pa.x][pb.x], b01 = S[pa.x][pb.y], b10 = S[pa.y][pb.x], b11 = S[pa.y][pb.y];
+      // rows: J_a^T B
+      const double r00 = ca * b00 - sa * b10, r01 = ca * b01 - sa * b11;
+      const double r10 = sa * b00 + ca * b10, r11 = sa * b01 + ca * b11;
+      // columns: (J_a^T B) J_b
+      S[pa.x][pb.x] = cb * r00 - sb * r01;
+      S[pa.x][pb.y] = sb * r00 + cb * r01;
+      S[pa.y][pb.x] = cb * r10 - sb * r11;
+      S[pa.y][pb.y] = sb * r10 + cb * r11;
     }
-    __syncthreads();
-    // columns p, q of S and E
+    // E: columns p, q of every row, eight per thread
     for (int e = tid; e < JB * JP; e += 256) {
-      const int k = e / JP, row = e % JP;
-      const int2 pq = circle_pair(JP, rr, k);
-      const double c = rc[k], s = rs[k], cm1 = rcm1[k];
-      const double x = S[row][pq.x], y = S[row][pq.y];
-      S[row][pq.x] = c * x - s * y;
-      S[row][pq.y] = s * x + c * y;
+      const int be = e / JP, row = e % JP;
+      const int2 pq = rpq[be];
+      const double c = rc[be], s = rs[be], cm1 = rcm1[be];
       const double dp = row == pq.x ? 1.0 : 0.0, dq = row == pq.y ? 1.0 : 0.0;
       const double vx = V[row][pq.x], vy = V[row][pq.y];
       V[row][pq.x] = (c * vx - s * vy) + (cm1 * dp - s * dq);
@@ -188,9 +209,14 @@ jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, d
     }
     __syncthreads();
   }
+  if (tid < JB && nrot) atomicAdd(&nrot_block, nrot);
   double *Eo = E_out + (long long)blockIdx.x * JP * JP;
   for (int e = tid; e < JP * JP; e += 256) Eo[e] = V[e / JP][e % JP];
-  if (tid < JB && nrot) atomicAdd(rotations, nrot);
+  __syncthreads();
+  if (tid == 0) {
+    active[blockIdx.x] = nrot_block > 0;
+    if (nrot_block) atomicAdd(rotations, nrot_block);
+  }
 }
 
 namespace {
@@ -224,11 +250,12 @@ __device__ __forceinline__ void tile_product(const double (*X)[JLD], const doubl
 // Round r's rotations applied to C (pair-blocks P <= Q, written to (P, Q) and
 // mirrored to (Q, P)) and to Y (64-row tiles), from E = V - I:
 //   C_PQ <- C_PQ + (T + E_P^T (C_PQ + T)),  T = C_PQ E_Q;   Y <- Y + Y E_Q.
-// Blocks [0, np*np) handle C, the next n_ytiles * np handle Y.
+// Blocks [0, np*np) handle C, the next n_ytiles * np handle Y; blocks whose
+// pairs applied no rotation leave their tile untouched.
 __global__ void __launch_bounds__(256)
 jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
-                    const double *__restrict__ Ep, double *__restrict__ Y, long long ldy,
-                    int n_aux) {
+                    const double *__restrict__ Ep, const int *__restrict__ active,
+                    double *__restrict__ Y, long long ldy, int n_aux, int *__restrict__ work) {
   __shared__ double X[JP][JLD];
   __shared__ double W[JP][JLD];
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
@@ -237,7 +264,9 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
   double acc[4][4], own[4][4];
   if (b < np * np) {
     const int P = b / np, Q = b % np;
-    if (P > Q) return;
+    // no rotation in either pair: V_P = V_Q = I exactly and C_PQ is unchanged
+    if (P > Q || (!active[P] && !active[Q])) return;
+    if (tid == 0) atomicAdd(&work[0], 1);
     const int2 IP = circle_pair(nb, r, P), IQ = circle_pair(nb, r, Q);
     const double *EQ = Ep + (long long)Q * JP * JP, *EP = Ep + (long long)P * JP * JP;
     for (int e = tid; e < JP * JP; e += 256) {
@@ -283,6 +312,8 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
   }
   b -= np * np;
   const int yt = b / np, Q = b % np;
+  if (!active[Q]) return;
+  if (tid == 0) atomicAdd(&work[1], 1);
   const int y0 = yt * JP;
   const int2 IQ = circle_pair(nb, r, Q);
   const double *EQ = Ep + (long long)Q * JP * JP;
@@ -303,8 +334,8 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
   }
 }
 
-__global__ void zero_counter_kernel(int *__restrict__ x) {
-  if (threadIdx.x == 0) x[0] = 0;
+__global__ void zero_counter_kernel(int *__restrict__ x, int n) {
+  if ((int)threadIdx.x < n) x[threadIdx.x] = 0;
 }
 
 // Omega_nu = sqrt(C_nu,nu) for nu < n (1 for the padding); omega_sorted gets
@@ -449,34 +480,36 @@ analytic_finish_kernel(const double2 *__restrict__ sigma, int n_real, const doub
 // ---------------------------------------------------------------------------
 // Launchers
 
-void launch_casida_operands(const double *M_ov, const double *eps, int n_aux, int n_occ, int n_virt,
-                            int ld, double *Vt, double *Y, hipStream_t s) {
+void launch_casida_operands(const double *M_ov, const double *eps, const int *perm, int n_aux,
+                            int n_occ, int n_virt, int ld, double *Vt, double *Y, hipStream_t s) {
   const long long total = (long long)n_aux * ld;
   const int grid = (int)std::min<long long>((total + 255) / 256, 65536);
-  casida_operands_kernel<<<grid, 256, 0, s>>>(M_ov, eps, n_aux, n_occ, n_virt, ld, Vt, Y);
+  casida_operands_kernel<<<grid, 256, 0, s>>>(M_ov, eps, perm, n_aux, n_occ, n_virt, ld, Vt, Y);
 }
 
 void launch_gemm_tn(const double *A, long long lda, const double *B, long long ldb, int M, int N,
-                    int K, double *out, long long ldo, const double *eps, int n_occ, int n_virt,
-                    int n_diag, hipStream_t s) {
+                    int K, double *out, long long ldo, const double *diag, int n_diag,
+                    hipStream_t s) {
   if (M < 1 || N < 1) return;
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
-  gemm_tn_kernel<<<grid, 256, 0, s>>>(A, lda, B, ldb, M, N, K, out, ldo, eps, n_occ, n_virt, n_diag);
+  gemm_tn_kernel<<<grid, 256, 0, s>>>(A, lda, B, ldb, M, N, K, out, ldo, diag, n_diag);
 }
 
 int jacobi_block() { return JB; }
 
-void launch_zero_counter(int *x, hipStream_t s) { zero_counter_kernel<<<1, 64, 0, s>>>(x); }
+void launch_zero_counters(int *x, int n, hipStream_t s) { zero_counter_kernel<<<1, 64, 0, s>>>(x, n); }
 
 void launch_jacobi_pairs(const double *C, long long ldc, int nb, int r, double tol, double *Ep,
-                         int *rotations, hipStream_t s) {
-  jacobi_pair_kernel<<<nb / 2, 256, 0, s>>>(C, ldc, nb, r, tol, Ep, rotations);
+                         int *active, int *rotations, hipStream_t s) {
+  jacobi_pair_kernel<<<nb / 2, 256, 0, s>>>(C, ldc, nb, r, tol, Ep, active, rotations);
 }
 
-void launch_jacobi_apply(double *C, long long ldc, int nb, int r, const double *Ep, double *Y,
-                         long long ldy, int n_aux, hipStream_t s) {
+void launch_jacobi_apply(double *C, long long ldc, int nb, int r, const double *Ep,
+                         const int *active, double *Y, long long ldy, int n_aux, int *work,
+                         hipStream_t s) {
   const int np = nb / 2, ytiles = (n_aux + JP - 1) / JP;
-  jacobi_apply_kernel<<<np * np + ytiles * np, 256, 0, s>>>(C, ldc, nb, r, Ep, Y, ldy, n_aux);
+  jacobi_apply_kernel<<<np * np + ytiles * np, 256, 0, s>>>(C, ldc, nb, r, Ep, active, Y, ldy,
+                                                            n_aux, work);
 }
 
 void launch_excitations(const double *C, long long ldc, int n, int n_pad, double *Om,
