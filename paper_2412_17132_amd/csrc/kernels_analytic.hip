@@ -221,28 +221,45 @@ jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, d
 
 namespace {
 
-// acc = X^T-or-X times W over the 64-wide LDS tiles: out[a][b] = sum_k L(a, k) W[k][b]
-// with L(a, k) = X[a][k] (trans = false) or X[k][a] (trans = true).
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// 64 x 64 x 64 product over LDS tiles on FP64 MFMA (v_mfma_f64_16x16x4f64):
+// out[a][b] = sum_k L(a, k) W[k][b] with L(a, k) = X[a][k] (TRANS false) or
+// X[k][a] (TRANS true).  Wave w owns the 32 x 32 quadrant (w / 2, w % 2) as
+// 2 x 2 MFMA tiles.  Operand layout: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; element r of lane l's accumulator is D[4 r + l / 16][l % 16].
 template <bool TRANS>
-__device__ __forceinline__ void tile_product(const double (*X)[JLD], const double (*W)[JLD], int tx,
-                                             int ty, double acc[4][4]) {
+__device__ __forceinline__ void tile_product(const double (*X)[JLD], const double (*W)[JLD],
+                                             int wave, int lane, d4 acc[2][2]) {
+  const int li = lane & 15, lk = lane >> 4;
+  const int qr = (wave >> 1) * 32, qc = (wave & 1) * 32;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-#pragma unroll 8
-  for (int k = 0; k < JP; ++k) {
-    double a[4], b[4];
+    for (int u = 0; u < 2; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < JP; k0 += 4) {
+    double a[2], b[2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = TRANS ? X[k][ty + 16 * u] : X[ty + 16 * u][k];
-      b[u] = W[k][tx + 16 * u];
+    for (int t = 0; t < 2; ++t) {
+      const int row = qr + 16 * t + li;
+      a[t] = TRANS ? X[k0 + lk][row] : X[row][k0 + lk];
+      b[t] = W[k0 + lk][qc + 16 * t + li];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+      for (int u = 0; u < 2; ++u)
+        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
   }
+}
+
+// Position of accumulator element (t, u, r) of this lane in the 64 x 64 tile.
+__device__ __forceinline__ int acc_row(int wave, int lane, int t, int r) {
+  return (wave >> 1) * 32 + 16 * t + 4 * r + (lane >> 4);
+}
+__device__ __forceinline__ int acc_col(int wave, int lane, int u) {
+  return (wave & 1) * 32 + 16 * u + (lane & 15);
 }
 
 }  // namespace
@@ -258,10 +275,10 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
                     double *__restrict__ Y, long long ldy, int n_aux, int *__restrict__ work) {
   __shared__ double X[JP][JLD];
   __shared__ double W[JP][JLD];
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int np = nb / 2;
   int b = blockIdx.x;
-  double acc[4][4], own[4][4];
+  d4 acc[2][2];
   if (b < np * np) {
     const int P = b / np, Q = b % np;
     // no rotation in either pair: V_P = V_Q = I exactly and C_PQ is unchanged
@@ -275,29 +292,37 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
       W[a][c] = EQ[e];
     }
     __syncthreads();
-    tile_product<false>(X, W, tx, ty, acc);  // T = C_PQ E_Q
+    tile_product<false>(X, W, wave, lane, acc);  // T = C_PQ E_Q
+    double own[2][2][4], tpart[2][2][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) own[u][v] = X[ty + 16 * u][tx + 16 * v];
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          own[t][u][q] = X[acc_row(wave, lane, t, q)][acc_col(wave, lane, u)];
+          tpart[t][u][q] = acc[t][u][q];
+        }
     __syncthreads();
-    double tpart[4][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        tpart[u][v] = acc[u][v];
-        X[ty + 16 * u][tx + 16 * v] = own[u][v] + acc[u][v];  // C_PQ V_Q
-      }
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          X[acc_row(wave, lane, t, q)][acc_col(wave, lane, u)] = own[t][u][q] + tpart[t][u][q];
     for (int e = tid; e < JP * JP; e += 256) W[e / JP][e % JP] = EP[e];
     __syncthreads();
-    tile_product<true>(W, X, tx, ty, acc);  // E_P^T (C_PQ V_Q)
+    tile_product<true>(W, X, wave, lane, acc);  // E_P^T (C_PQ V_Q)
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        X[ty + 16 * u][tx + 16 * v] = own[u][v] + (tpart[u][v] + acc[u][v]);
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          X[acc_row(wave, lane, t, q)][acc_col(wave, lane, u)] =
+              own[t][u][q] + (tpart[t][u][q] + acc[t][u][q]);
     __syncthreads();
     for (int e = tid; e < JP * JP; e += 256) {
       const int a = e / JP, c = e % JP;
@@ -323,15 +348,19 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
     W[a][c] = EQ[e];
   }
   __syncthreads();
-  tile_product<false>(X, W, tx, ty, acc);  // Y_tile E_Q
+  tile_product<false>(X, W, wave, lane, acc);  // Y_tile E_Q
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int row = y0 + ty + 16 * u;
-    if (row >= n_aux) continue;
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      Y[(long long)row * ldy + pair_index(IQ, tx + 16 * v)] = X[ty + 16 * u][tx + 16 * v] + acc[u][v];
-  }
+    for (int q = 0; q < 4; ++q) {
+      const int lr = acc_row(wave, lane, t, q), row = y0 + lr;
+      if (row >= n_aux) continue;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int lc = acc_col(wave, lane, u);
+        Y[(long long)row * ldy + pair_index(IQ, lc)] = X[lr][lc] + acc[t][u][q];
+      }
+    }
 }
 
 __global__ void zero_counter_kernel(int *__restrict__ x, int n) {
