@@ -25,12 +25,15 @@ Contents
                moments (Eq. density_shifts), the pole sum of Eq. sigma_spectral
                and the G0W0 / G_DH W0 spectral functions (Eqs.
                A_explicit_real_imaginary, hedin_sigma_spectral).
+* `evgw`     - evGW0 (Eq. ev_sigma_spectral): every state's quasiparticle
+               equation iterated with the current energies in G and W at the
+               RPA level, by a bracketed Newton solve per state.
 
 Parity status of every function is stated in its docstring; none is
 "parity unpinned" (each is pinned by tests under `tests/test_oracle_*.py`).
 """
-from . import analytic, cumulant, sigma, wac  # noqa: F401
+from . import analytic, cumulant, evgw, sigma, wac  # noqa: F401
 from .cumulant import spectral_cumulant
 from .sigma import sigma_core
 
-__all__ = ["sigma", "cumulant", "wac", "analytic", "sigma_core", "spectral_cumulant"]
+__all__ = ["sigma", "cumulant", "wac", "analytic", "evgw", "sigma_core", "spectral_cumulant"]

@@ -6,7 +6,7 @@ reference) and the GPU binding consume what it produces; neither imports
 the other.
 """
 from .configs import CONFIGS, EV_PER_HA, WorkloadConfig, serving_request_config
-from .generate import System, make_system, mgl_grid, system_from_config
+from .generate import System, make_system, make_vv, mgl_grid, system_from_config, vv_block
 
 __all__ = [
     "CONFIGS",
@@ -14,7 +14,9 @@ __all__ = [
     "WorkloadConfig",
     "System",
     "make_system",
+    "make_vv",
     "mgl_grid",
     "serving_request_config",
     "system_from_config",
+    "vv_block",
 ]

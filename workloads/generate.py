@@ -15,6 +15,11 @@ All energies are converted to Hartree (1 Ha = 27.211386245988 eV); M is in
 Ha^(1/2).  Optionally (`structured=True`) the core/other-orbital coefficients
 M_{c,m != c} are scaled by 1e-3 to mimic core localisation.
 
+The virtual-virtual block M_vv (needed only when the energies of virtual
+states are themselves updated, as in evGW0) comes from its own stream,
+`Generator(PCG64(SeedSequence([seed, 2])))`, with the same scale and the
+upper triangle (a <= b) mirrored, so that adding it changes no other array.
+
 Grids: the imaginary axis uses the modified Gauss-Legendre mapping of
 `mgl_grid`; the real axis is an inclusive linspace either on an absolute eV
 window shared by all cores, or on [eps_n + lo, eps_n + hi] per core n (so the
@@ -44,6 +49,8 @@ class System:
     eta: float
     vxc: Optional[np.ndarray] = None
     name: str = ""
+    seed: Optional[int] = None
+    m_scale: float = 0.3
 
     @property
     def n_aux(self) -> int:
@@ -127,7 +134,25 @@ def make_system(n_basis: int, n_occ: int, n_core: int, n_aux: int, n_imag: int, 
     return System(eps=eps, occ=occ, M_oo=np.ascontiguousarray(M_oo),
                   M_ov=np.ascontiguousarray(M_ov), core_idx=core_idx,
                   omega_imag=omega_imag, w_imag=w_imag, omega_real=omega_real,
-                  eta=eta_ev / EV_PER_HA, vxc=None, name=name)
+                  eta=eta_ev / EV_PER_HA, vxc=None, name=name, seed=seed, m_scale=m_scale)
+
+
+def make_vv(n_aux: int, n_virt: int, seed: int, m_scale: float = 0.3) -> np.ndarray:
+    """M_vv[P][a][b] ~ N(0,1) * m_scale / sqrt(N_aux), symmetric in (a, b)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 2])))
+    raw = rng.standard_normal((n_aux, n_virt, n_virt)) * (m_scale / np.sqrt(n_aux))
+    iu = np.triu_indices(n_virt)
+    M_vv = np.zeros_like(raw)
+    M_vv[:, iu[0], iu[1]] = raw[:, iu[0], iu[1]]
+    M_vv[:, iu[1], iu[0]] = raw[:, iu[0], iu[1]]
+    return np.ascontiguousarray(M_vv)
+
+
+def vv_block(system: System) -> np.ndarray:
+    """The M_vv block belonging to a generated system (its seed and scale)."""
+    if system.seed is None:
+        raise ValueError("system has no seed")
+    return make_vv(system.n_aux, system.n_virt, system.seed, system.m_scale)
 
 
 def system_from_config(cfg: WorkloadConfig, structured: bool = False, **over) -> System:
