@@ -393,6 +393,8 @@ def main():
                     help="skip the DECOUPLED-mode leg reported beside the FULL value")
     ap.add_argument("--no-analytic", action="store_true",
                     help="skip the fully analytic G0W0 leg (Casida eigensolve + pole sums)")
+    ap.add_argument("--no-evgw", action="store_true",
+                    help="skip the evGW0 leg (all states' energies iterated; M_vv of the workload)")
     ap.add_argument("--sample-points", type=int, default=0,
                     help="sampled run for large workloads (c3, c4): one core state at 1 and this "
                          "many real points, extrapolated to the full grid")
@@ -657,6 +659,31 @@ def main():
                              "unit": "TFLOP/s", "frac": ja_tf / FP64_VECTOR_PEAK_TFLOPS},
             "jacobi_pairs_ms_per_step": jp["total_ms"] / args.steps,
             "e_qp_dev_from_cd_mev": float(deq.max() * EV_PER_HA * 1e3),
+        }
+    if args.mode == "full" and not args.no_evgw:
+        from workloads import vv_block
+        dvv = torch.as_tensor(vv_block(s), device=dev)
+
+        def evstep():
+            return gwc.gwc_evgw0(d["eps"], d["occ"], d["M_oo"], d["M_ov"], dvv, d["core_idx"],
+                                 d["omega_real"], d["eta"])
+        evstep()  # warm-up
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        for _ in range(args.steps):
+            eout = evstep()
+        torch.cuda.synchronize()
+        el_e = time.perf_counter() - te
+        eq = eout["e_qp"].cpu().numpy()
+        e1 = eout["e_first"].cpu().numpy()
+        core = s.core_idx
+        res["evgw0"] = {
+            "value": solves / el_e, "unit": "solves/s (core states, every state iterated)",
+            "ms_per_step": el_e / args.steps * 1e3,
+            "states_iterated": int(s.n_basis), "outer_iterations": int(eout["outer"][0]),
+            "max_newton_steps": int(eout["newton"].max()),
+            "core_shift_g0w0_ev": [float(x) for x in (e1[core] - s.eps[core]) * EV_PER_HA],
+            "core_shift_evgw0_ev": [float(x) for x in (eq[core] - s.eps[core]) * EV_PER_HA],
         }
     if not args.no_peaks:
         pk = measure_peaks(gwc)

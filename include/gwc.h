@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define GWC_VERSION 10200 /* 1.2.0 */
+#define GWC_VERSION 10300 /* 1.3.0 */
 
 enum gwc_status {
   GWC_OK = 0,
@@ -288,6 +288,74 @@ typedef struct {
  * (GWC_ERR_SHAPE otherwise).  Returns GWC_OK or a negative gwc_status. */
 int gwc_sigma_analytic(const gwc_system *sys, const gwc_analytic_args *args, gwc_analytic_out *out,
                        void *hip_stream);
+
+/* Settings of gwc_evgw0 (all > 0; GWC_ERR_INVALID_ARG otherwise). */
+typedef struct {
+  int32_t max_outer;   /* outer iterations on the energies in G */
+  double tol_outer;    /* stop when max_n |e^(k+1)_n - e^(k)_n| < tol_outer (Ha) */
+  int32_t max_newton;  /* Newton steps per state and iteration after bracketing */
+  double tol_newton;   /* a state's solve ends when |Delta E| < tol_newton (Ha) */
+} gwc_evgw_params;
+
+/* Arguments of gwc_evgw0.
+ *   M_vv       [n_aux][n_virt][n_virt]  RI coefficients M^P_ab (symmetric in a, b):
+ *                                       every state's energy is updated, so pairs
+ *                                       of two virtual states occur (required)
+ *   core_idx   [n_core]                 occupied states whose Sigma^c,ev and A are
+ *                                       returned on omega_real [n_core][n_real]
+ *                                       (strictly increasing per core)
+ *   eta > 0                             broadening of the poles
+ *   vxc        [n_basis] or NULL        <n|v_xc|n> of every state, NULL means 0
+ *   params     NULL: max_outer 100, tol_outer 1e-8, max_newton 200, tol_newton 1e-10 */
+typedef struct {
+  const double *M_vv;
+  int32_t n_core;
+  const int32_t *core_idx;
+  int32_t n_real;
+  const double *omega_real;
+  double eta;
+  const double *vxc;
+  const gwc_evgw_params *params;
+} gwc_evgw_args;
+
+/* Outputs of gwc_evgw0 (each may be host or device memory).
+ *   e_qp     [n_basis]                 evGW0 quasiparticle energies (required)
+ *   e_first  [n_basis]                 energies after the first iteration (the G0W0
+ *                                      solutions found from eps), or NULL
+ *   sigma_x  [n_basis]                 Sigma^x_n = -sum_i (n i|i n), or NULL
+ *   sigma_c  [n_core][n_real][2]       Sigma^c,ev_n(w) with the final energies in G, or NULL
+ *   a_ev     [n_core][n_real]          A of Eq. A_explicit_real_imaginary with Sigma^x +
+ *                                      Sigma^c,ev, or NULL
+ *   newton   [n_basis] int32           Newton steps of each state in the last iteration,
+ *                                      -1 where max_newton did not converge, or NULL
+ *   outer    [1] int32                 iterations taken, -1 when max_outer did not
+ *                                      converge (the last iterate is returned), or NULL */
+typedef struct {
+  double *e_qp;
+  double *e_first;
+  double *sigma_x;
+  double *sigma_c;
+  double *a_ev;
+  int32_t *newton;
+  int32_t *outer;
+} gwc_evgw_out;
+
+/* Eigenvalue-self-consistent evGW0 (paper section "GW for core levels: beyond
+ * G0W0", Eq. ev_sigma_spectral): with Omega^nu and rho^nu_nm of the RPA on the
+ * mean-field energies (as in gwc_sigma_analytic, for every pair of states),
+ *   Sigma^c,ev_n(w; e) = sum_{m,nu} (rho^nu_nm)^2 / (w - e_m + (Omega^nu - i eta) s_m),
+ *   s_m = +1 for occupied, -1 for virtual m,
+ * every state's quasiparticle equation (Eq. quasiparticle_equation)
+ *   E = eps_n + Sigma^x_n + Re Sigma^c,ev_n(E; e^(k)) - v^xc_n
+ * is solved from E0 = e^(k)_n (e^(0) = eps): points E0 + d eta 2^j, d = -sign f(E0),
+ * until f changes sign, then Newton steps (analytic derivative) from the bracket's
+ * midpoint, each replaced by the midpoint when it leaves the shrinking bracket;
+ * e^(k+1) = the roots, until max_n |e^(k+1)_n - e^(k)_n| < tol_outer.
+ * Device memory ~ 8 (n_basis^2 (n_ov + n_aux) + n_ov^2 + 3 n_aux n_ov) bytes,
+ * n_ov = n_occ * n_virt <= 65536.  Non-convergence is reported in `outer` and
+ * `newton`, not as an error.  Returns GWC_OK or a negative gwc_status. */
+int gwc_evgw0(const gwc_system *sys, const gwc_evgw_args *args, gwc_evgw_out *out,
+              void *hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Device-resident systems (serving form).  gwc_system_create validates a

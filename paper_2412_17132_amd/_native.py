@@ -45,6 +45,7 @@ EXPORTED_SYMBOLS = (
     "gwc_server_destroy",
     "gwc_probe_peak",
     "gwc_sigma_analytic",
+    "gwc_evgw0",
 )
 
 
@@ -97,6 +98,25 @@ class GwcAnalyticOut(Structure):
         ("sigma_c", c_void_p), ("sigma_c_eps", c_void_p), ("sigma_x", c_void_p),
         ("e_qp", c_void_p), ("a_gw", c_void_p), ("a_dh", c_void_p), ("omega_exc", c_void_p),
         ("sweeps", c_void_p),
+    ]
+
+
+class GwcEvgwParams(Structure):
+    _fields_ = [("max_outer", c_int32), ("tol_outer", c_double), ("max_newton", c_int32),
+                ("tol_newton", c_double)]
+
+
+class GwcEvgwArgs(Structure):
+    _fields_ = [
+        ("M_vv", c_void_p), ("n_core", c_int32), ("core_idx", c_void_p), ("n_real", c_int32),
+        ("omega_real", c_void_p), ("eta", c_double), ("vxc", c_void_p), ("params", c_void_p),
+    ]
+
+
+class GwcEvgwOut(Structure):
+    _fields_ = [
+        ("e_qp", c_void_p), ("e_first", c_void_p), ("sigma_x", c_void_p), ("sigma_c", c_void_p),
+        ("a_ev", c_void_p), ("newton", c_void_p), ("outer", c_void_p),
     ]
 
 
@@ -197,6 +217,9 @@ def load(path: str = LIB_PATH):
     lib.gwc_sigma_analytic.argtypes = [POINTER(GwcSystem), POINTER(GwcAnalyticArgs),
                                        POINTER(GwcAnalyticOut), c_void_p]
     lib.gwc_sigma_analytic.restype = c_int
+    lib.gwc_evgw0.argtypes = [POINTER(GwcSystem), POINTER(GwcEvgwArgs), POINTER(GwcEvgwOut),
+                              c_void_p]
+    lib.gwc_evgw0.restype = c_int
     lib.gwc_probe_peak.argtypes = [c_int, POINTER(c_double), c_void_p]
     lib.gwc_probe_peak.restype = c_int
     _lib = lib

@@ -136,6 +136,44 @@ def gwc_sigma_analytic(eps, occ, M_oo, M_ov, core_idx, omega_real, eta, vxc=None
     return out
 
 
+def gwc_evgw0(eps, occ, M_oo, M_ov, M_vv, core_idx, omega_real, eta, vxc=None, params=None,
+              out: Optional[dict] = None, stream=None) -> dict:
+    """evGW0 quasiparticle energies of every state (gwc_evgw0, Eq. ev_sigma_spectral).
+
+    vxc: optional [n_basis]; params: optional dict (max_outer, tol_outer,
+    max_newton, tol_newton).  Returns a dict with e_qp, e_first, sigma_x
+    [n_basis], sigma_c [n_core][n_real][2], a_ev [n_core][n_real], newton
+    [n_basis] and outer [1] (int32)."""
+    import ctypes
+    lib = N.load()
+    n_aux, n_occ, n_virt = (int(s) for s in M_ov.shape)
+    nb = n_occ + n_virt
+    n_core = int(core_idx.shape[0])
+    n_real = int(omega_real.shape[-1])
+    keep: list = []
+    sys = N.GwcSystem(n_aux, n_occ, n_virt, _as_arg(eps, "f8", keep), _as_arg(occ, "f8", keep),
+                      _as_arg(M_oo, "f8", keep), _as_arg(M_ov, "f8", keep))
+    pp = None
+    if params is not None:
+        p = N.GwcEvgwParams(int(params["max_outer"]), float(params["tol_outer"]),
+                            int(params["max_newton"]), float(params["tol_newton"]))
+        keep.append(p)
+        pp = ctypes.addressof(p)
+    args = N.GwcEvgwArgs(_as_arg(M_vv, "f8", keep), n_core, _as_arg(core_idx, "i4", keep), n_real,
+                         _as_arg(omega_real, "f8", keep), float(eta), _as_arg(vxc, "f8", keep), pp)
+    if out is None:
+        out = {
+            "e_qp": _alloc((nb,), M_ov), "e_first": _alloc((nb,), M_ov),
+            "sigma_x": _alloc((nb,), M_ov), "sigma_c": _alloc((n_core, n_real, 2), M_ov),
+            "a_ev": _alloc((n_core, n_real), M_ov), "newton": _alloc((nb,), M_ov, integer=True),
+            "outer": np.zeros(1, dtype=np.int32),
+        }
+    o = N.GwcEvgwOut(*(_as_out(out.get(k)) for k in
+                       ("e_qp", "e_first", "sigma_x", "sigma_c", "a_ev", "newton", "outer")))
+    N.check(lib.gwc_evgw0(sys, args, o, _stream_handle(stream)))
+    return out
+
+
 def wac_paper_settings(n_core_pts: int = 100, n_val_pts: int = 100) -> dict:
     """The paper's CD-WAC settings (section "Computational Details"): 100 core-window
     and 100 valence-window points, core window 0..40 eV, valence margins 8 % below

@@ -1010,21 +1010,19 @@ AnalyticInputs check_analytic_args(int n_occ, long long n_ov, const gwc_analytic
   return in;
 }
 
-void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analytic_out *out,
-                  hipStream_t s) {
-  const AnalyticInputs in = check_analytic_args(rs.no, rs.n_ov, args, out, s);
-  const std::vector<int> &core = in.core;
-  const std::vector<double> &wr = in.wr, &vxc = in.vxc;
-  const int nc = args->n_core, nr = args->n_real;
-  const int N = rs.N, no = rs.no, nv = rs.nv, nbas = rs.nb, n = rs.n_ov;
+// RPA excitations of a resident system (Eqs. rpa_casida, rpa_matrices, symmetric
+// form): the Casida matrix C is built and diagonalised by block Jacobi with
+// the rotations carried into Y = Delta^1/2 L.  On return dY holds R = Y Z
+// (n_aux x n_pad, row stride n_pad), dOm the excitation energies Omega in the
+// rotated order (n_pad, 1 on the padding) and dsort (if non-NULL) the n_ov
+// energies in ascending order.  Returns n_pad.
+int rpa_solve(ResidentSystem &rs, hipStream_t s, DevBuf &dY, DevBuf &dOm, DevBuf *dsort, int &sweeps) {
+  const int N = rs.N, no = rs.no, nv = rs.nv, n = rs.n_ov;
   const int JB2 = 2 * jacobi_block();
   const int n_pad = (int)round_up(n, JB2), nblk = n_pad / jacobi_block(), np = nblk / 2;
   const long long ld = n_pad;
 
-  DevBuf dcore(s), dwr(s), dvxc(s), dC(s), dVt(s), dY(s), dVp(s), dact(s), drot(s), dOm(s), dsort(s);
-  const int *d_core = upload(dcore, core, s);
-  const double *d_wr = upload(dwr, wr, s);
-  const double *d_vxc = upload(dvxc, vxc, s);
+  DevBuf dC(s), dVt(s), dVp(s), dact(s), drot(s);
   dC.alloc((size_t)n_pad * n_pad * sizeof(double));
   dVt.alloc((size_t)N * n_pad * sizeof(double));
   dY.alloc((size_t)N * n_pad * sizeof(double));
@@ -1032,9 +1030,8 @@ void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analyti
   dact.alloc((size_t)np * sizeof(int));
   drot.alloc(3 * sizeof(int));  // rotations, C tiles and Y tiles updated in a sweep
   dOm.alloc((size_t)n_pad * sizeof(double));
-  dsort.alloc((size_t)n * sizeof(double));
+  if (dsort) dsort->alloc((size_t)n * sizeof(double));
   double *C = dC.as<double>(), *Y = dY.as<double>();
-
   // transitions ordered by Delta, so that near-degenerate ones share Jacobi blocks
   std::vector<int> perm(n);
   std::vector<double> delta(n), diag2(n);
@@ -1059,7 +1056,8 @@ void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analyti
   // flops of one updated tile: C tiles two 64^3 products, Y tiles one
   const double fl_ctile = 4.0 * JB2 * JB2 * JB2, fl_ytile = 2.0 * JB2 * JB2 * JB2;
   const double fl_pairs = (double)np * (JB2 - 1) * 18.0 * jacobi_block() * JB2;
-  int sweeps = 0, counts[3] = {1, 0, 0};
+  sweeps = 0;
+  int counts[3] = {1, 0, 0};
   constexpr int kMaxSweeps = 60;
   while (counts[0] != 0) {
     if (sweeps == kMaxSweeps) fail(GWC_ERR_FACTORIZATION, "block Jacobi not converged after %d sweeps", kMaxSweeps);
@@ -1085,7 +1083,7 @@ void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analyti
     timing_resolve(pending);
   }
 
-  launch_excitations(C, ld, n, n_pad, dOm.as<double>(), dsort.as<double>(), s);
+  launch_excitations(C, ld, n, n_pad, dOm.as<double>(), dsort ? dsort->as<double>() : nullptr, s);
   {
     DevBuf dflag(s);
     dflag.alloc(sizeof(int));
@@ -1097,6 +1095,24 @@ void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analyti
     if (flag) fail(GWC_ERR_FACTORIZATION, "non-positive eigenvalue of the Casida matrix");
   }
   dC.release();
+  return n_pad;
+}
+
+void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analytic_out *out,
+                  hipStream_t s) {
+  const AnalyticInputs in = check_analytic_args(rs.no, rs.n_ov, args, out, s);
+  const std::vector<int> &core = in.core;
+  const std::vector<double> &wr = in.wr, &vxc = in.vxc;
+  const int nc = args->n_core, nr = args->n_real;
+  const int N = rs.N, no = rs.no, nv = rs.nv, nbas = rs.nb, n = rs.n_ov;
+
+  DevBuf dcore(s), dwr(s), dvxc(s), dY(s), dOm(s), dsort(s);
+  const int *d_core = upload(dcore, core, s);
+  const double *d_wr = upload(dwr, wr, s);
+  const double *d_vxc = upload(dvxc, vxc, s);
+  int sweeps = 0;
+  const long long ld = rpa_solve(rs, s, dY, dOm, &dsort, sweeps);
+  const double *Y = dY.as<double>();
 
   // Q[c nb + m][nu] = sum_P M^P_{n_c m} R[P][nu], R = Y after the rotations
   DevBuf dBp(s), dQ(s), dpart(s), dsig(s), dsx(s), dsc(s), dse(s), deq(s), dagw(s), dadh(s);
@@ -1109,7 +1125,7 @@ void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analyti
   dpart.alloc((size_t)pole_sum_blocks(n) * nc * npts * sizeof(double2));
   dsig.alloc((size_t)nc * npts * sizeof(double2));
   launch_pole_sum(dQ.as<double>(), n, dOm.as<double>(), n, rs.d_eps.as<double>(), no, nbas, d_core,
-                  nc, d_wr, nr, args->eta, dpart.as<double2>(), dsig.as<double2>(), s);
+                  nc, d_wr, nr, args->eta, 0, nullptr, dpart.as<double2>(), dsig.as<double2>(), s);
   dsx.alloc(nc * sizeof(double));
   launch_sigma_x(rs.d_Moo.as<double>(), N, no, d_core, nc, dsx.as<double>(), s);
   dsc.alloc((size_t)nc * nr * 2 * sizeof(double));
@@ -1129,6 +1145,141 @@ void run_analytic(ResidentSystem &rs, const gwc_analytic_args *args, gwc_analyti
   copy_out(out->a_dh, dadh.p, (size_t)nc * nr * sizeof(double), s);
   copy_out(out->omega_exc, dsort.p, (size_t)n * sizeof(double), s);
   if (out->sweeps) copy_out(out->sweeps, &sweeps, sizeof(int32_t), s);
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+struct EvgwInputs {
+  std::vector<int> core;
+  std::vector<double> wr, vxc;
+  gwc_evgw_params p{100, 1e-8, 200, 1e-10};
+};
+
+// Host-side checks of gwc_evgw0's arguments (no device work).
+EvgwInputs check_evgw_args(int n_occ, int n_basis, long long n_ov, const gwc_evgw_args *args,
+                           const gwc_evgw_out *out, hipStream_t s) {
+  if (!args || !out) fail(GWC_ERR_INVALID_ARG, "NULL args or out");
+  if (!out->e_qp) fail(GWC_ERR_INVALID_ARG, "e_qp is required");
+  if (!args->M_vv) fail(GWC_ERR_INVALID_ARG, "M_vv is required");
+  const int nc = args->n_core, nr = args->n_real;
+  if (nc < 1 || nr < 1) fail(GWC_ERR_SHAPE, "n_core, n_real must be >= 1");
+  if (!args->core_idx || !args->omega_real) fail(GWC_ERR_INVALID_ARG, "NULL input array");
+  if (!std::isfinite(args->eta)) fail(GWC_ERR_NONFINITE, "non-finite eta");
+  if (!(args->eta > 0.0)) fail(GWC_ERR_INVALID_ARG, "eta must be > 0");
+  if (n_ov > 65536) fail(GWC_ERR_SHAPE, "n_occ * n_virt = %lld exceeds 65536", n_ov);
+  EvgwInputs in;
+  if (args->params) {
+    in.p = *args->params;
+    if (!std::isfinite(in.p.tol_outer) || !std::isfinite(in.p.tol_newton))
+      fail(GWC_ERR_NONFINITE, "non-finite evGW0 tolerance");
+    if (in.p.max_outer < 1 || in.p.max_newton < 1 || !(in.p.tol_outer > 0.0) || !(in.p.tol_newton > 0.0))
+      fail(GWC_ERR_INVALID_ARG, "evGW0 settings need max_outer, max_newton >= 1 and tolerances > 0");
+  }
+  in.core = to_host(args->core_idx, nc, s);
+  in.wr = to_host(args->omega_real, (size_t)nc * nr, s);
+  in.vxc.assign(n_basis, 0.0);
+  if (args->vxc) in.vxc = to_host(args->vxc, n_basis, s);
+  if (!all_finite(in.wr) || !all_finite(in.vxc)) fail(GWC_ERR_NONFINITE, "non-finite value in omega_real or vxc");
+  for (int c = 0; c < nc; ++c) {
+    if (in.core[c] < 0 || in.core[c] >= n_occ) fail(GWC_ERR_SHAPE, "core_idx[%d] = %d not in [0, n_occ)", c, in.core[c]);
+    for (int j = 1; j < nr; ++j)
+      if (!(in.wr[(size_t)c * nr + j] > in.wr[(size_t)c * nr + j - 1]))
+        fail(GWC_ERR_INVALID_ARG, "omega_real of core %d must increase", c);
+  }
+  return in;
+}
+
+// evGW0 (kernels_evgw.hip): the RPA once, rho^2 for every pair of states, then
+// the outer iteration over all states' quasiparticle equations.
+void run_evgw0(ResidentSystem &rs, const gwc_evgw_args *args, gwc_evgw_out *out, hipStream_t s) {
+  const EvgwInputs in = check_evgw_args(rs.no, rs.nb, rs.n_ov, args, out, s);
+  const int nc = args->n_core, nr = args->n_real;
+  const int N = rs.N, no = rs.no, nv = rs.nv, nbas = rs.nb, n = rs.n_ov;
+
+  DevBuf dvv(s), dcore(s), dwr(s), dvxc(s), dY(s), dOm(s);
+  const size_t n_vv = (size_t)N * nv * nv;
+  dvv.alloc(n_vv * sizeof(double));
+  HIPCHECK(hipMemcpyAsync(dvv.p, args->M_vv, n_vv * sizeof(double), hipMemcpyDefault, s));
+  {
+    DevBuf dflag(s);
+    dflag.alloc(sizeof(int));
+    HIPCHECK(hipMemsetAsync(dflag.p, 0, sizeof(int), s));
+    launch_nonfinite(dvv.as<double>(), (long long)n_vv, dflag.as<int>(), s);
+    int flag = 0;
+    HIPCHECK(hipMemcpyAsync(&flag, dflag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (flag) fail(GWC_ERR_NONFINITE, "non-finite value in M_vv");
+  }
+  const int *d_core = upload(dcore, in.core, s);
+  const double *d_wr = upload(dwr, in.wr, s);
+  const double *d_vxc = upload(dvxc, in.vxc, s);
+  int sweeps = 0;
+  const long long ld = rpa_solve(rs, s, dY, dOm, nullptr, sweeps);
+
+  // rho^2[(n nb + m)][nu] for every pair of states
+  const long long rows = (long long)nbas * nbas;
+  DevBuf dR2(s), dsx(s);
+  {
+    DevBuf dBp(s);
+    dBp.alloc((size_t)N * rows * sizeof(double));
+    dR2.alloc((size_t)rows * n * sizeof(double));
+    launch_pack_all_pairs(rs.d_Moo.as<double>(), rs.d_Mov.as<double>(), dvv.as<double>(), N, no, nv,
+                          dBp.as<double>(), s);
+    launch_gemm_tn(dBp.as<double>(), rows, dY.as<double>(), ld, (int)rows, n, N, dR2.as<double>(), n,
+                   nullptr, 0, s);
+    launch_square_moments(dR2.as<double>(), rows, n, dOm.as<double>(), s);
+    HIPCHECK(hipGetLastError());
+  }
+  dY.release();
+  dvv.release();
+  dsx.alloc((size_t)nbas * sizeof(double));
+  launch_exchange_all(rs.d_Moo.as<double>(), rs.d_Mov.as<double>(), N, no, nv, dsx.as<double>(), s);
+
+  // outer iteration on the energies in G
+  DevBuf de(s), denew(s), dsteps(s);
+  de.alloc((size_t)nbas * sizeof(double));
+  denew.alloc((size_t)nbas * sizeof(double));
+  dsteps.alloc((size_t)nbas * sizeof(int));
+  HIPCHECK(hipMemcpyAsync(de.p, rs.d_eps.p, (size_t)nbas * sizeof(double), hipMemcpyDeviceToDevice, s));
+  std::vector<double> e_host(rs.eps), e_new(nbas), e_first;
+  int outer = -1;
+  for (int k = 0; k < in.p.max_outer; ++k) {
+    launch_ev_solve(dR2.as<double>(), n, dOm.as<double>(), rs.d_eps.as<double>(), de.as<double>(),
+                    dsx.as<double>(), d_vxc, nbas, no, args->eta, in.p.tol_newton, in.p.max_newton,
+                    denew.as<double>(), dsteps.as<int>(), s);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(e_new.data(), denew.p, (size_t)nbas * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(de.p, denew.p, (size_t)nbas * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    double delta = 0.0;
+    for (int m = 0; m < nbas; ++m) delta = std::max(delta, std::fabs(e_new[m] - e_host[m]));
+    if (!all_finite(e_new)) fail(GWC_ERR_NONFINITE, "non-finite quasiparticle energy in evGW0");
+    e_host = e_new;
+    if (k == 0) e_first = e_new;
+    if (delta < in.p.tol_outer) {
+      outer = k + 1;
+      break;
+    }
+  }
+
+  // Sigma^c,ev and A of the core states with the final energies in G
+  const int npts = nr + 1;
+  DevBuf dpart(s), dsig(s), dsc(s), daev(s);
+  dpart.alloc((size_t)pole_sum_blocks(n) * nc * npts * sizeof(double2));
+  dsig.alloc((size_t)nc * npts * sizeof(double2));
+  launch_pole_sum(dR2.as<double>(), n, dOm.as<double>(), n, de.as<double>(), no, nbas, d_core, nc,
+                  d_wr, nr, args->eta, 1, d_core, dpart.as<double2>(), dsig.as<double2>(), s);
+  dsc.alloc((size_t)nc * nr * 2 * sizeof(double));
+  daev.alloc((size_t)nc * nr * sizeof(double));
+  launch_ev_finish(dsig.as<double2>(), nc, nr, rs.d_eps.as<double>(), d_core, d_wr, dsx.as<double>(),
+                   d_vxc, dsc.as<double>(), daev.as<double>(), s);
+  HIPCHECK(hipGetLastError());
+  copy_out(out->e_qp, de.p, (size_t)nbas * sizeof(double), s);
+  copy_out(out->e_first, e_first.data(), (size_t)nbas * sizeof(double), s);
+  copy_out(out->sigma_x, dsx.p, (size_t)nbas * sizeof(double), s);
+  copy_out(out->sigma_c, dsc.p, (size_t)nc * nr * 2 * sizeof(double), s);
+  copy_out(out->a_ev, daev.p, (size_t)nc * nr * sizeof(double), s);
+  copy_out(out->newton, dsteps.p, (size_t)nbas * sizeof(int32_t), s);
+  if (out->outer) copy_out(out->outer, &outer, sizeof(int32_t), s);
   HIPCHECK(hipStreamSynchronize(s));
 }
 
@@ -1218,6 +1369,19 @@ int gwc_sigma_analytic(const gwc_system *sys, const gwc_analytic_args *args, gwc
     (void)gwc::check_analytic_args(sys->n_occ, (long long)sys->n_occ * sys->n_virt, args, out, s);
     std::unique_ptr<gwc::ResidentSystem> rs(gwc::create_resident(sys, s));
     gwc::run_analytic(*rs, args, out, s);
+    return GWC_OK;
+  });
+}
+
+int gwc_evgw0(const gwc_system *sys, const gwc_evgw_args *args, gwc_evgw_out *out,
+              void *hip_stream) {
+  return guarded([&] {
+    if (!sys || !args || !out) fail(GWC_ERR_INVALID_ARG, "NULL system, args or out");
+    hipStream_t s = (hipStream_t)hip_stream;
+    (void)gwc::check_evgw_args(sys->n_occ, sys->n_occ + sys->n_virt,
+                               (long long)sys->n_occ * sys->n_virt, args, out, s);
+    std::unique_ptr<gwc::ResidentSystem> rs(gwc::create_resident(sys, s));
+    gwc::run_evgw0(*rs, args, out, s);
     return GWC_OK;
   });
 }

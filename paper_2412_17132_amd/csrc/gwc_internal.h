@@ -128,14 +128,31 @@ void launch_excitations(const double *C, long long ldc, int n, int n_pad, double
                         double *sorted, hipStream_t s);
 void launch_pack_pairs(const double *M_oo, const double *M_ov, int n_aux, int n_occ, int n_virt,
                        const int *core, int n_core, double *Bp, hipStream_t s);
-// part holds pole_sum_blocks(n_ov) x n_core x (n_real + 1) double2.
+// part holds pole_sum_blocks(n_ov) x n_core x (n_real + 1) double2.  Q rows
+// (c or row_state[c]) * n_basis + m hold projected densities, or rho^2 when
+// `squared`; eps are the energies in G.
 int pole_sum_blocks(int n_ov);
 void launch_pole_sum(const double *Q, long long ldq, const double *Om, int n_ov, const double *eps,
                      int n_occ, int n_basis, const int *core, int n_core, const double *omega_real,
-                     int n_real, double eta, double2 *part, double2 *sigma, hipStream_t s);
+                     int n_real, double eta, int squared, const int *row_state, double2 *part,
+                     double2 *sigma, hipStream_t s);
 void launch_analytic_finish(const double2 *sigma, int n_core, int n_real, const double *eps,
                             const int *core, const double *omega_real, const double *sigma_x,
                             const double *vxc, double *sigma_c, double *sigma_c_eps, double *e_qp,
                             double *a_gw, double *a_dh, hipStream_t s);
+
+// evGW0 (kernels_evgw.hip).
+void launch_pack_all_pairs(const double *M_oo, const double *M_ov, const double *M_vv, int n_aux,
+                           int n_occ, int n_virt, double *Bp, hipStream_t s);
+void launch_square_moments(double *Q, long long rows, int n_ov, const double *Om, hipStream_t s);
+void launch_exchange_all(const double *M_oo, const double *M_ov, int n_aux, int n_occ, int n_virt,
+                         double *sx, hipStream_t s);
+void launch_ev_solve(const double *r2, int n_ov, const double *Om, const double *eps,
+                     const double *e, const double *sx, const double *vxc, int nb, int n_occ,
+                     double eta, double tol, int max_steps, double *e_new, int *steps,
+                     hipStream_t s);
+void launch_ev_finish(const double2 *sigma, int n_core, int n_real, const double *eps,
+                      const int *core, const double *omega_real, const double *sx,
+                      const double *vxc, double *sigma_c, double *a_ev, hipStream_t s);
 
 }  // namespace gwc

@@ -410,12 +410,15 @@ pack_pairs_kernel(const double *__restrict__ M_oo, const double *__restrict__ M_
 // 64 (blockIdx.x) for core c (blockIdx.y) at points j (blockIdx.z * 256 + tid):
 // point j < n_real is omega_real[c][j], j = n_real is eps_{n_c}.
 //   term = rho^2 / (a - i s eta), a = w - eps_m + s Omega, s = +1 (occupied m) / -1,
-//   rho^2 = 2 Q[c nb + m][nu]^2 / Omega_nu.
+//   rho^2 = 2 Q[r + m][nu]^2 / Omega_nu, or Q[r + m][nu] itself when `squared`;
+//   row base r = c nb, or row_state[c] nb when row_state is given.
+// eps holds the energies in G (eps_m); point n_real is w = eps[core[c]].
 __global__ void __launch_bounds__(256)
 pole_sum_kernel(const double *__restrict__ Q, long long ldq, const double *__restrict__ Om, int n_ov,
                 const double *__restrict__ eps, int n_occ, int n_basis,
                 const int *__restrict__ core, const double *__restrict__ omega_real, int n_real,
-                double eta, double2 *__restrict__ part) {
+                double eta, int squared, const int *__restrict__ row_state,
+                double2 *__restrict__ part) {
   constexpr int MB = 16, VB = 64;
   __shared__ double r2[MB][VB + 1];
   __shared__ double oms[VB];
@@ -433,8 +436,9 @@ pole_sum_kernel(const double *__restrict__ Q, long long ldq, const double *__res
       const int mm = e / VB, v = e % VB, m = m0 + mm, nu = v0 + v;
       double x = 0.0;
       if (m < n_basis && nu < n_ov) {
-        const double q = Q[((long long)c * n_basis + m) * ldq + nu];
-        x = 2.0 * q * q / Om[nu];
+        const long long r0 = (long long)(row_state ? row_state[c] : c) * n_basis;
+        const double q = Q[(r0 + m) * ldq + nu];
+        x = squared ? q : 2.0 * q * q / Om[nu];
       }
       r2[mm][v] = x;
     }
@@ -558,11 +562,12 @@ int pole_sum_blocks(int n_ov) { return (n_ov + 63) / 64; }
 
 void launch_pole_sum(const double *Q, long long ldq, const double *Om, int n_ov, const double *eps,
                      int n_occ, int n_basis, const int *core, int n_core, const double *omega_real,
-                     int n_real, double eta, double2 *part, double2 *sigma, hipStream_t s) {
+                     int n_real, double eta, int squared, const int *row_state, double2 *part,
+                     double2 *sigma, hipStream_t s) {
   const int nblk = pole_sum_blocks(n_ov), npts = n_real + 1;
   dim3 grid(nblk, n_core, (npts + 255) / 256);
   pole_sum_kernel<<<grid, 256, 0, s>>>(Q, ldq, Om, n_ov, eps, n_occ, n_basis, core, omega_real,
-                                       n_real, eta, part);
+                                       n_real, eta, squared, row_state, part);
   pole_reduce_kernel<<<(n_core * npts + 255) / 256, 256, 0, s>>>(part, nblk, n_core, npts, sigma);
 }
 

@@ -160,3 +160,26 @@ def test_sigma_analytic_argument_errors(gwc, case, status):
     with pytest.raises(gwc.GwcError) as ei:
         gwc.gwc_sigma_analytic(**kw)
     assert ei.value.status == status, str(ei.value)
+
+
+@pytest.mark.parametrize("case,status", [
+    ("no_vv", -1), ("core", -2), ("eta", -1), ("params", -1), ("gap", -3),
+])
+def test_evgw0_argument_errors(gwc, case, status):
+    from workloads import vv_block
+    s = _sys()
+    kw = dict(eps=s.eps, occ=s.occ, M_oo=s.M_oo, M_ov=s.M_ov, M_vv=vv_block(s),
+              core_idx=s.core_idx, omega_real=s.omega_real, eta=s.eta)
+    if case == "no_vv":
+        kw["M_vv"] = None
+    elif case == "core":
+        kw["core_idx"] = np.array([5], dtype=np.int32)   # a virtual state
+    elif case == "eta":
+        kw["eta"] = 0.0
+    elif case == "params":
+        kw["params"] = dict(max_outer=0, tol_outer=1e-8, max_newton=10, tol_newton=1e-10)
+    elif case == "gap":
+        s.eps[2] = s.eps[3] + 0.01
+    with pytest.raises(gwc.GwcError) as ei:
+        gwc.gwc_evgw0(**kw)
+    assert ei.value.status == status, str(ei.value)
