@@ -19,7 +19,7 @@ namespace gwc {
 
 namespace {
 
-constexpr int EVT = 256;  // threads per state
+constexpr int EVT = 1024;  // threads per state
 
 // Re Sigma and d Re Sigma / dE of one state at E (all threads receive them).
 __device__ void ev_sigma(const double *__restrict__ r2row, int n_ov, const double *__restrict__ Om,

@@ -22,11 +22,14 @@ TOL = 1e-9
 
 CASES = [
     # n_occ, n_virt, n_aux, n_core, n_real, seed: n_ov = 15 (one block pair), 92, 205
-    # (ragged against the 64-wide pair blocks), 279 with 3 cores
+    # (ragged against the 64-wide pair blocks), 279 with 3 cores, exactly 64 (no
+    # padding), 65 (one padded pair block) and a single real point
     (3, 5, 12, 1, 9, 11),
     (4, 23, 50, 2, 17, 5),
     (5, 41, 90, 1, 33, 7),
     (9, 31, 120, 3, 70, 13),
+    (2, 32, 40, 1, 5, 19),
+    (5, 13, 40, 2, 1, 21),
 ]
 
 

@@ -24,7 +24,8 @@ torch = pytest.importorskip("torch")
 TOL = 1e-9
 
 CASES = [
-    # n_occ, n_virt, n_aux, n_core, n_real, seed
+    # n_occ, n_virt, n_aux, n_core, n_real, seed; one virtual state and one real point
+    (3, 1, 10, 1, 1, 13),
     (4, 12, 30, 2, 5, 9),
     (5, 14, 40, 2, 9, 23),
     (12, 90, 300, 3, 17, 31),
