@@ -16,7 +16,8 @@
 // (63 rounds of 32 disjoint plane rotations) and stores the accumulated
 // orthogonal V_p as E_p = V_p - I (kept exactly: c - 1 = -s^2 / (1 + c));
 // jacobi_apply_kernel then forms C <- V^T C V block by block (only pair-blocks
-// P <= Q, mirrored) and Y <- Y V as corrections,
+// P <= Q; C is kept as its upper triangle of 32 x 32 blocks) and Y <- Y V as
+// corrections,
 //   V_P^T C V_Q = C + (C E_Q + E_P^T (C + C E_Q)),   Y V_Q = Y + Y E_Q,
 // so that an element is rounded once per round relative to its own size and
 // not once per product term; a round without rotations leaves C exact.  A
@@ -45,6 +46,44 @@ __device__ __forceinline__ int2 circle_pair(int m, int r, int k) {
 // Global index of row/column t (< 64) of the submatrix of block pair (I, J).
 __device__ __forceinline__ int pair_index(int2 IJ, int t) {
   return t < JB ? IJ.x * JB + t : IJ.y * JB + (t - JB);
+}
+
+// During the sweeps the symmetric C is kept as its upper triangle of 32 x 32
+// blocks: block (X, Y) is stored when X <= Y and a lower block is read through
+// its mirror.  The logical 64 x 64 tile with the rows of pair R and the
+// columns of pair K is moved as four 32 x 32 sub-blocks; consecutive threads
+// touch consecutive addresses in both orientations.
+__device__ __forceinline__ void load_pair_tile(const double *__restrict__ C, long long ldc, int2 R,
+                                               int2 K, double (*T)[JLD]) {
+  for (int e = threadIdx.x; e < JP * JP; e += blockDim.x) {
+    const int sub = e / (JB * JB), w = e % (JB * JB);
+    const int sa = sub >> 1, sc = sub & 1;
+    const int rb = sa ? R.y : R.x, cb = sc ? K.y : K.x;
+    const int u = w / JB, v = w % JB;
+    if (rb <= cb) T[sa * JB + u][sc * JB + v] = C[(long long)(rb * JB + u) * ldc + cb * JB + v];
+    else T[sa * JB + v][sc * JB + u] = C[(long long)(cb * JB + u) * ldc + rb * JB + v];
+  }
+}
+
+// Writes the logical tile T back into the stored triangle.  For a diagonal
+// pair tile (same pair as rows and columns) the lower off-diagonal sub-block
+// is left to its mirror and the two diagonal 32-blocks are written symmetrised.
+__device__ __forceinline__ void store_pair_tile(double *__restrict__ C, long long ldc, int2 R,
+                                                int2 K, bool same, const double (*T)[JLD]) {
+  for (int e = threadIdx.x; e < JP * JP; e += blockDim.x) {
+    const int sub = e / (JB * JB), w = e % (JB * JB);
+    const int sa = sub >> 1, sc = sub & 1;
+    const int rb = sa ? R.y : R.x, cb = sc ? K.y : K.x;
+    const int u = w / JB, v = w % JB;
+    if (rb == cb) {
+      const int o = sa * JB;
+      C[(long long)(rb * JB + u) * ldc + cb * JB + v] = u <= v ? T[o + u][o + v] : T[o + v][o + u];
+    } else if (rb < cb) {
+      C[(long long)(rb * JB + u) * ldc + cb * JB + v] = T[sa * JB + u][sc * JB + v];
+    } else if (!same) {
+      C[(long long)(cb * JB + u) * ldc + rb * JB + v] = T[sa * JB + v][sc * JB + u];
+    }
+  }
 }
 
 }  // namespace
@@ -141,11 +180,8 @@ jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, d
   __shared__ int nrot_block;
   const int tid = threadIdx.x;
   const int2 IJ = circle_pair(nb, r, blockIdx.x);
-  for (int e = tid; e < JP * JP; e += 256) {
-    const int a = e / JP, b = e % JP;
-    S[a][b] = C[(long long)pair_index(IJ, a) * ldc + pair_index(IJ, b)];
-    V[a][b] = 0.0;
-  }
+  load_pair_tile(C, ldc, IJ, IJ, S);
+  for (int e = tid; e < JP * JP; e += 256) V[e / JP][e % JP] = 0.0;
   if (tid == 0) nrot_block = 0;
   __syncthreads();
   // a submatrix already diagonal to the threshold needs no sweep: E = 0
@@ -264,8 +300,8 @@ __device__ __forceinline__ int acc_col(int wave, int lane, int u) {
 
 }  // namespace
 
-// Round r's rotations applied to C (pair-blocks P <= Q, written to (P, Q) and
-// mirrored to (Q, P)) and to Y (64-row tiles), from E = V - I:
+// Round r's rotations applied to C (pair-blocks P <= Q, each 32-block written
+// once into the stored triangle) and to Y (64-row tiles), from E = V - I:
 //   C_PQ <- C_PQ + (T + E_P^T (C_PQ + T)),  T = C_PQ E_Q;   Y <- Y + Y E_Q.
 // Blocks [0, np*np) handle C, the next n_ytiles * np handle Y; blocks whose
 // pairs applied no rotation leave their tile untouched.
@@ -286,11 +322,8 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
     if (tid == 0) atomicAdd(&work[0], 1);
     const int2 IP = circle_pair(nb, r, P), IQ = circle_pair(nb, r, Q);
     const double *EQ = Ep + (long long)Q * JP * JP, *EP = Ep + (long long)P * JP * JP;
-    for (int e = tid; e < JP * JP; e += 256) {
-      const int a = e / JP, c = e % JP;
-      X[a][c] = C[(long long)pair_index(IP, a) * ldc + pair_index(IQ, c)];
-      W[a][c] = EQ[e];
-    }
+    load_pair_tile(C, ldc, IP, IQ, X);
+    for (int e = tid; e < JP * JP; e += 256) W[e / JP][e % JP] = EQ[e];
     __syncthreads();
     tile_product<false>(X, W, wave, lane, acc);  // T = C_PQ E_Q
     double own[2][2][4], tpart[2][2][4];
@@ -324,15 +357,7 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
           X[acc_row(wave, lane, t, q)][acc_col(wave, lane, u)] =
               own[t][u][q] + (tpart[t][u][q] + acc[t][u][q]);
     __syncthreads();
-    for (int e = tid; e < JP * JP; e += 256) {
-      const int a = e / JP, c = e % JP;
-      if (P == Q) {
-        C[(long long)pair_index(IP, a) * ldc + pair_index(IP, c)] = a <= c ? X[a][c] : X[c][a];
-      } else {
-        C[(long long)pair_index(IP, a) * ldc + pair_index(IQ, c)] = X[a][c];
-        C[(long long)pair_index(IQ, a) * ldc + pair_index(IP, c)] = X[c][a];
-      }
-    }
+    store_pair_tile(C, ldc, IP, IQ, P == Q, X);
     return;
   }
   b -= np * np;
