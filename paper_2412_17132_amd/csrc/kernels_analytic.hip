@@ -259,13 +259,39 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// 64 x 64 x 64 product over LDS tiles on FP64 MFMA (v_mfma_f64_16x16x4f64):
-// out[a][b] = sum_k L(a, k) W[k][b] with L(a, k) = X[a][k] (TRANS false) or
-// X[k][a] (TRANS true).  Wave w owns the 32 x 32 quadrant (w / 2, w % 2) as
-// 2 x 2 MFMA tiles.  Operand layout: lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; element r of lane l's accumulator is D[4 r + l / 16][l % 16].
-template <bool TRANS>
-__device__ __forceinline__ void tile_product(const double (*X)[JLD], const double (*W)[JLD],
+// 64 x 64 x 64 products on FP64 MFMA (v_mfma_f64_16x16x4f64) with one operand
+// a 64 x 64 tile in LDS and the other a rotation correction E (row-major
+// 64 x 64, read straight from L2: every tile of a round shares it):
+//   prod_tile_e:  out = X E        (X in LDS)
+//   prod_et_tile: out = E^T X      (X in LDS)
+// Wave w owns the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 MFMA tiles.  Operand
+// layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; element r of
+// lane l's accumulator is D[4 r + l / 16][l % 16].
+__device__ __forceinline__ void prod_tile_e(const double (*X)[JLD], const double *__restrict__ E,
+                                            int wave, int lane, d4 acc[2][2]) {
+  const int li = lane & 15, lk = lane >> 4;
+  const int qr = (wave >> 1) * 32, qc = (wave & 1) * 32;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < JP; k0 += 4) {
+    double a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = X[qr + 16 * t + li][k0 + lk];
+      b[t] = E[(k0 + lk) * JP + qc + 16 * t + li];
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void prod_et_tile(const double *__restrict__ E, const double (*X)[JLD],
                                              int wave, int lane, d4 acc[2][2]) {
   const int li = lane & 15, lk = lane >> 4;
   const int qr = (wave >> 1) * 32, qc = (wave & 1) * 32;
@@ -278,9 +304,8 @@ __device__ __forceinline__ void tile_product(const double (*X)[JLD], const doubl
     double a[2], b[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      const int row = qr + 16 * t + li;
-      a[t] = TRANS ? X[k0 + lk][row] : X[row][k0 + lk];
-      b[t] = W[k0 + lk][qc + 16 * t + li];
+      a[t] = E[(k0 + lk) * JP + qr + 16 * t + li];
+      b[t] = X[k0 + lk][qc + 16 * t + li];
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -310,7 +335,6 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
                     const double *__restrict__ Ep, const int *__restrict__ active,
                     double *__restrict__ Y, long long ldy, int n_aux, int *__restrict__ work) {
   __shared__ double X[JP][JLD];
-  __shared__ double W[JP][JLD];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int np = nb / 2;
   int b = blockIdx.x;
@@ -323,9 +347,8 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
     const int2 IP = circle_pair(nb, r, P), IQ = circle_pair(nb, r, Q);
     const double *EQ = Ep + (long long)Q * JP * JP, *EP = Ep + (long long)P * JP * JP;
     load_pair_tile(C, ldc, IP, IQ, X);
-    for (int e = tid; e < JP * JP; e += 256) W[e / JP][e % JP] = EQ[e];
     __syncthreads();
-    tile_product<false>(X, W, wave, lane, acc);  // T = C_PQ E_Q
+    prod_tile_e(X, EQ, wave, lane, acc);  // T = C_PQ E_Q
     double own[2][2][4], tpart[2][2][4];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -344,9 +367,8 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           X[acc_row(wave, lane, t, q)][acc_col(wave, lane, u)] = own[t][u][q] + tpart[t][u][q];
-    for (int e = tid; e < JP * JP; e += 256) W[e / JP][e % JP] = EP[e];
     __syncthreads();
-    tile_product<true>(W, X, wave, lane, acc);  // E_P^T (C_PQ V_Q)
+    prod_et_tile(EP, X, wave, lane, acc);  // E_P^T (C_PQ V_Q)
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -370,10 +392,9 @@ jacobi_apply_kernel(double *__restrict__ C, long long ldc, int nb, int r,
   for (int e = tid; e < JP * JP; e += 256) {
     const int a = e / JP, c = e % JP;
     X[a][c] = (y0 + a < n_aux) ? Y[(long long)(y0 + a) * ldy + pair_index(IQ, c)] : 0.0;
-    W[a][c] = EQ[e];
   }
   __syncthreads();
-  tile_product<false>(X, W, wave, lane, acc);  // Y_tile E_Q
+  prod_tile_e(X, EQ, wave, lane, acc);  // Y_tile E_Q
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
