@@ -36,6 +36,7 @@ constexpr int JP = 2 * JB;      // pair submatrix order
 constexpr int JLD = JP + 1;     // LDS row stride (bank spread)
 constexpr int GT = 64;          // gemm tile
 constexpr int GK = 16;          // gemm K chunk
+constexpr int JPT = 1024;       // threads of the pair-sweep kernel
 
 // Round-robin (circle) pairing of m items: round r in [0, m-1), slot k in [0, m/2).
 __device__ __forceinline__ int2 circle_pair(int m, int r, int k) {
@@ -170,7 +171,7 @@ gemm_tn_kernel(const double *__restrict__ A, long long lda, const double *__rest
 // J_alpha^T S_ab J_beta with J = [[c, s], [-s, c]], and E's columns p, q follow
 // V's (d = the identity's columns):
 //   E_p <- c E_p - s E_q + (c - 1) d_p - s d_q,  E_q <- s E_p + c E_q + s d_p + (c - 1) d_q.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(JPT)
 jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, double tol,
                    double *__restrict__ E_out, int *__restrict__ active, int *__restrict__ rotations) {
   __shared__ double S[JP][JLD];
@@ -181,19 +182,19 @@ jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, d
   const int tid = threadIdx.x;
   const int2 IJ = circle_pair(nb, r, blockIdx.x);
   load_pair_tile(C, ldc, IJ, IJ, S);
-  for (int e = tid; e < JP * JP; e += 256) V[e / JP][e % JP] = 0.0;
+  for (int e = tid; e < JP * JP; e += JPT) V[e / JP][e % JP] = 0.0;
   if (tid == 0) nrot_block = 0;
   __syncthreads();
   // a submatrix already diagonal to the threshold needs no sweep: E = 0
   int big = 0;
-  for (int e = tid; e < JP * JP; e += 256) {
+  for (int e = tid; e < JP * JP; e += JPT) {
     const int a = e / JP, b = e % JP;
     const double x = S[a][b];
     big |= a < b && x != 0.0 && fabs(x) > tol * sqrt(fabs(S[a][a] * S[b][b]));
   }
   if (!__syncthreads_or(big)) {
     double *Eo = E_out + (long long)blockIdx.x * JP * JP;
-    for (int e = tid; e < JP * JP; e += 256) Eo[e] = 0.0;
+    for (int e = tid; e < JP * JP; e += JPT) Eo[e] = 0.0;
     if (tid == 0) active[blockIdx.x] = 0;
     return;
   }
@@ -219,7 +220,7 @@ jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, d
     }
     __syncthreads();
     // S: 2 x 2 blocks (alpha, beta), four per thread
-    for (int e = tid; e < JB * JB; e += 256) {
+    for (int e = tid; e < JB * JB; e += JPT) {
       const int al = e / JB, be = e % JB;
       const int2 pa = rpq[al], pb = rpq[be];
       const double ca = rc[al], sa = rs[al], cb = rc[be], sb = rs[be];
@@ -234,7 +235,7 @@ jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, d
       S[pa.y][pb.y] = sb * r10 + cb * r11;
     }
     // E: columns p, q of every row, eight per thread
-    for (int e = tid; e < JB * JP; e += 256) {
+    for (int e = tid; e < JB * JP; e += JPT) {
       const int be = e / JP, row = e % JP;
       const int2 pq = rpq[be];
       const double c = rc[be], s = rs[be], cm1 = rcm1[be];
@@ -247,7 +248,7 @@ jacobi_pair_kernel(const double *__restrict__ C, long long ldc, int nb, int r, d
   }
   if (tid < JB && nrot) atomicAdd(&nrot_block, nrot);
   double *Eo = E_out + (long long)blockIdx.x * JP * JP;
-  for (int e = tid; e < JP * JP; e += 256) Eo[e] = V[e / JP][e % JP];
+  for (int e = tid; e < JP * JP; e += JPT) Eo[e] = V[e / JP][e % JP];
   __syncthreads();
   if (tid == 0) {
     active[blockIdx.x] = nrot_block > 0;
@@ -580,7 +581,7 @@ void launch_zero_counters(int *x, int n, hipStream_t s) { zero_counter_kernel<<<
 
 void launch_jacobi_pairs(const double *C, long long ldc, int nb, int r, double tol, double *Ep,
                          int *active, int *rotations, hipStream_t s) {
-  jacobi_pair_kernel<<<nb / 2, 256, 0, s>>>(C, ldc, nb, r, tol, Ep, active, rotations);
+  jacobi_pair_kernel<<<nb / 2, JPT, 0, s>>>(C, ldc, nb, r, tol, Ep, active, rotations);
 }
 
 void launch_jacobi_apply(double *C, long long ldc, int nb, int r, const double *Ep,
