@@ -35,10 +35,10 @@ void launch_chi(const double *eps, int n_occ, int n_virt, const double2 *z, int 
 void launch_pi_build_f64(const double *Lp, int ldl, int n_aux, const double *chi_re,
                          const double *chi_im, int F, const int2 *tiles, int n_tiles,
                          double2 *G, long long g_stride, int ldg, hipStream_t stream);
-// Mixed-precision Pi build (prec 1 = BF16X3, 2 = FP16X3).  Tiles are 64 x 256
+// Mixed-precision Pi build (prec 1 = BF16X3, 2 = FP16X3).  Tiles are 128 x 256
 // blocks (MX_TILE_ROWS x MX_TILE_COLS); the split operands have their rows
 // padded to a multiple of MX_TILE_COLS.
-constexpr int MX_TILE_ROWS = 64;
+constexpr int MX_TILE_ROWS = 128;
 constexpr int MX_TILE_COLS = 256;
 // prec 1 BF16X3, 2 FP16X3, 3 FP8X3; Bhi / Blo hold 16-bit (1, 2) or 8-bit (3)
 // elements.

@@ -16,9 +16,10 @@
 //   FP8X3:  fp8 e4m3 (4-bit significand, largest 448) with the same scaling
 //           aimed one binade higher -> ~2^-7 relative per product
 //
-// Tile: one 64 x 256 block of Pi per workgroup and frequency (4 waves of
+// Tile: one 128 x 256 block of Pi per workgroup and frequency (8 waves of
 // 32 x 128, v_mfma_f32_16x16x32_{bf16,f16}), upper-triangle blocks only, the
 // result written as 1 - Pi (FP64) into the bordered matrix with its mirror.
+// Every B chunk staged in LDS serves 128 rows.
 #include "gwc_internal.h"
 
 namespace gwc {
@@ -32,11 +33,11 @@ typedef unsigned char uc8 __attribute__((ext_vector_type(8)));
 // fp8 e4m3 (the MFMA's fp8 operand format on this target)
 struct e4m3 {};
 
-constexpr int MX_TR = 64;    // tile rows
+constexpr int MX_TR = MX_TILE_ROWS;  // tile rows
 constexpr int MX_TC = MX_TILE_COLS;  // tile columns
 constexpr int MX_NB = MX_TC / 32;      // 16-column blocks per wave (a wave covers MX_TC / 2)
 constexpr int MX_KC = 32;    // K per LDS stage
-constexpr int MX_THREADS = 256;
+constexpr int MX_THREADS = 512;
 
 // 16-bit splits (round to nearest even)
 __device__ __forceinline__ unsigned short to_bits(__bf16 x) { return __builtin_bit_cast(unsigned short, x); }
@@ -170,7 +171,7 @@ __global__ void taskscale_kernel(const double *__restrict__ chi_re, const double
 // MFMA layout (16x16x32): lane l supplies A[l%16][8(l/16)+e], B[8(l/16)+e][l%16];
 // output element r of lane l is D[4(l/16)+r][l%16].
 template <class T>
-__global__ void __launch_bounds__(MX_THREADS, 2)
+__global__ void __launch_bounds__(MX_THREADS, 1)
 pi_build_mixed_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__restrict__ Bhi,
                       const typename Mix<T>::E *__restrict__ Blo, int ldl, int n_aux,
                       const double *__restrict__ chi_re, const double *__restrict__ chi_im,
