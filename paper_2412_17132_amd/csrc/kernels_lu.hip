@@ -510,20 +510,17 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   double2 *A = G + (long long)f * gs;
 
-  d4 cre[2][2], cim[2][2];
+  // complex product in three real MFMA products (Gauss):
+  //   P1 = L_r U_r, P2 = L_i U_i, P3 = (L_r + L_i)(U_r + U_i),
+  //   (L U)_r = P1 - P2, (L U)_i = P3 - P1 - P2
+  d4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const int col = ca + wc + 16 * b + li;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = ra + wr + 16 * a + 4 * r + lk;
-        double2 v = make_double2(0.0, 0.0);
-        if (row < n && col < col_end) v = A[(long long)row * ldg + col];
-        cre[a][b][r] = v.x;
-        cim[a][b][r] = v.y;
-      }
+      p1[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      p2[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      p3[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     }
 #pragma unroll 4
   for (int kk = 0; kk < klen; kk += 4) {
@@ -541,13 +538,13 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const double ar = -lv[a].x, ai = -lv[a].y;
+      const double ls = lv[a].x + lv[a].y;
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv[b].x, cre[a][b], 0, 0, 0);
-        cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[a].y, uv[b].y, cre[a][b], 0, 0, 0);
-        cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv[b].y, cim[a][b], 0, 0, 0);
-        cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, uv[b].x, cim[a][b], 0, 0, 0);
+        const double us = uv[b].x + uv[b].y;
+        p1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[a].x, uv[b].x, p1[a][b], 0, 0, 0);
+        p2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[a].y, uv[b].y, p2[a][b], 0, 0, 0);
+        p3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ls, us, p3[a][b], 0, 0, 0);
       }
     }
   }
@@ -559,7 +556,11 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = ra + wr + 16 * a + 4 * r + lk;
-        if (row < n && col < col_end) A[(long long)row * ldg + col] = make_double2(cre[a][b][r], cim[a][b][r]);
+        if (row < n && col < col_end) {
+          double2 &x = A[(long long)row * ldg + col];
+          const double q1 = p1[a][b][r], q2 = p2[a][b][r];
+          x = make_double2(x.x - (q1 - q2), x.y - (p3[a][b][r] - q1 - q2));
+        }
       }
     }
 }
