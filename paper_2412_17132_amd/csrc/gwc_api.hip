@@ -372,11 +372,12 @@ const MixedOperands &mixed_operands(ResidentSystem &rs, int prec, hipStream_t s)
   launch_mixed_prep(prec, rs.d_L.as<double>(), rs.n_aux_pad, rows_pad, rs.ldl, m.Lf.as<float>(),
                     m.Bh.p, m.Bl.p, m.cs.as<float>(), m.ics.as<float>(), m.acol.as<float>(), s);
   std::vector<int2> mt;
-  const int nr_t = (rs.N + MX_TILE_ROWS - 1) / MX_TILE_ROWS;
+  const int tr = mixed_tile_rows(prec);
+  const int nr_t = (rs.N + tr - 1) / tr;
   const int nc_t = (rs.N + MX_TILE_COLS - 1) / MX_TILE_COLS;
   for (int i = 0; i < nr_t; ++i)
     for (int j = 0; j < nc_t; ++j)
-      if ((j + 1) * MX_TILE_COLS > i * MX_TILE_ROWS) mt.push_back(make_int2(i, j));
+      if ((j + 1) * MX_TILE_COLS > i * tr) mt.push_back(make_int2(i, j));
   upload(m.tiles, mt, s);
   m.n_tiles = (int)mt.size();
   HIPCHECK(hipGetLastError());

@@ -35,11 +35,11 @@ void launch_chi(const double *eps, int n_occ, int n_virt, const double2 *z, int 
 void launch_pi_build_f64(const double *Lp, int ldl, int n_aux, const double *chi_re,
                          const double *chi_im, int F, const int2 *tiles, int n_tiles,
                          double2 *G, long long g_stride, int ldg, hipStream_t stream);
-// Mixed-precision Pi build (prec 1 = BF16X3, 2 = FP16X3).  Tiles are 128 x 256
-// blocks (MX_TILE_ROWS x MX_TILE_COLS); the split operands have their rows
-// padded to a multiple of MX_TILE_COLS.
-constexpr int MX_TILE_ROWS = 128;
+// Mixed-precision Pi build.  Tiles are mixed_tile_rows(prec) x MX_TILE_COLS
+// blocks (128 x 256 for the 16-bit forms, 64 x 256 for FP8); the split operands
+// have their rows padded to a multiple of MX_TILE_COLS.
 constexpr int MX_TILE_COLS = 256;
+constexpr int mixed_tile_rows(int prec) { return prec == 3 ? 64 : 128; }
 // prec 1 BF16X3, 2 FP16X3, 3 FP8X3; Bhi / Blo hold 16-bit (1, 2) or 8-bit (3)
 // elements.
 void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, float *Lf,

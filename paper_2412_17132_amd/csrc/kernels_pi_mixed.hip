@@ -16,10 +16,12 @@
 //   FP8X3:  fp8 e4m3 (4-bit significand, largest 448) with the same scaling
 //           aimed one binade higher -> ~2^-7 relative per product
 //
-// Tile: one 128 x 256 block of Pi per workgroup and frequency (8 waves of
-// 32 x 128, v_mfma_f32_16x16x32_{bf16,f16}), upper-triangle blocks only, the
-// result written as 1 - Pi (FP64) into the bordered matrix with its mirror.
-// Every B chunk staged in LDS serves 128 rows.
+// Tile: one 128 x 256 block of Pi per workgroup and frequency for the 16-bit
+// forms (8 waves of 32 x 128, v_mfma_f32_16x16x32_{bf16,f16}; every B chunk
+// staged in LDS serves 128 rows), 64 x 256 with 4 waves for FP8 (whose B chunk
+// is half the bytes, so occupancy pays more than reuse); upper-triangle blocks
+// only, the result written as 1 - Pi (FP64) into the bordered matrix with its
+// mirror.
 #include "gwc_internal.h"
 
 namespace gwc {
@@ -33,11 +35,9 @@ typedef unsigned char uc8 __attribute__((ext_vector_type(8)));
 // fp8 e4m3 (the MFMA's fp8 operand format on this target)
 struct e4m3 {};
 
-constexpr int MX_TR = MX_TILE_ROWS;  // tile rows
 constexpr int MX_TC = MX_TILE_COLS;  // tile columns
 constexpr int MX_NB = MX_TC / 32;      // 16-column blocks per wave (a wave covers MX_TC / 2)
 constexpr int MX_KC = 32;    // K per LDS stage
-constexpr int MX_THREADS = 512;
 
 // 16-bit splits (round to nearest even)
 __device__ __forceinline__ unsigned short to_bits(__bf16 x) { return __builtin_bit_cast(unsigned short, x); }
@@ -94,6 +94,12 @@ struct Mix<e4m3> {
 };
 
 // ---------------------------------------------------------------------------
+// Tile rows per form (threads = 4 x rows: one wave per 16 rows).
+template <class T>
+constexpr int mx_rows() { return 128; }
+template <>
+constexpr int mx_rows<e4m3>() { return 64; }
+
 // Per-call preparation: FP32 copy of L (A source) and the split B operand,
 // all [rows_pad][ldl] with rows beyond n_aux_pad zero.  For FP16 and FP8 each
 // column k carries the scale 2^e_k (max_P |L_Pk| 2^e_k in the form's target
@@ -171,7 +177,7 @@ __global__ void taskscale_kernel(const double *__restrict__ chi_re, const double
 // MFMA layout (16x16x32): lane l supplies A[l%16][8(l/16)+e], B[8(l/16)+e][l%16];
 // output element r of lane l is D[4(l/16)+r][l%16].
 template <class T>
-__global__ void __launch_bounds__(MX_THREADS, 1)
+__global__ void __launch_bounds__(4 * mx_rows<T>(), 512 / (4 * mx_rows<T>()))
 pi_build_mixed_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__restrict__ Bhi,
                       const typename Mix<T>::E *__restrict__ Blo, int ldl, int n_aux,
                       const double *__restrict__ chi_re, const double *__restrict__ chi_im,
@@ -183,7 +189,8 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__
   constexpr int EP = 16 / (int)sizeof(E);  // elements per 16-byte load
   // B rows padded by 16 bytes (rows stay 16-byte aligned)
   constexpr int KC = MX_KC, LA = KC + 4, LB = KC + EP;
-  __shared__ float As[MX_TR * LA];
+  constexpr int TR = mx_rows<T>(), NT = 4 * TR;
+  __shared__ float As[TR * LA];
   __shared__ E Bh[MX_TC * LB];
   __shared__ E Bl[MX_TC * LB];
   __shared__ float Cr[KC], Ci[KC];
@@ -191,7 +198,7 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int2 tb = tiles[blockIdx.x];
-  const int P0 = tb.x * MX_TR, Q0 = tb.y * MX_TC;
+  const int P0 = tb.x * TR, Q0 = tb.y * MX_TC;
   const int f = blockIdx.y;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * (MX_TC / 2);
   const float gsc = tscale ? tscale[f] : 1.0f;
@@ -208,10 +215,10 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__
   const double *cr_g = chi_re + (long long)f * ldl;
   const double *ci_g = chi_im + (long long)f * ldl;
   for (int kc = 0; kc < ldl; kc += KC) {
-    // A source: 64 rows x 32 floats (8 per thread as two float4)
+    // A source: TR rows x 32 floats (8 per thread as two float4)
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
-      const int idx = it * MX_THREADS + tid;       // 0..511
+      const int idx = it * NT + tid;       // 0 .. 8 TR - 1
       const int row = idx >> 3, kq = (idx & 7) * 4;
       const float4 v = *reinterpret_cast<const float4 *>(Lf + (long long)(P0 + row) * ldl + kc + kq);
       float *dst = As + row * LA + kq;
@@ -219,8 +226,8 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__
     }
     // B: MX_TC rows x 32 elements, hi and lo (16 B per thread and pass)
 #pragma unroll
-    for (int it = 0; it < MX_TC * KC / (EP * MX_THREADS); ++it) {
-      const int idx = it * MX_THREADS + tid;
+    for (int it = 0; it < MX_TC * KC / (EP * NT); ++it) {
+      const int idx = it * NT + tid;
       const int row = idx / (KC / EP), kq = (idx % (KC / EP)) * EP;
       const long long off = (long long)(Q0 + row) * ldl + kc + kq;
       const uint4 vh = *reinterpret_cast<const uint4 *>(Bhi + off);
@@ -323,16 +330,16 @@ void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const voi
   dim3 grid(n_tiles, F);
   if (prec == 2) {
     taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, Mix<_Float16>::TARGET, acol, tscale);
-    pi_build_mixed_kernel<_Float16><<<grid, MX_THREADS, 0, stream>>>(
+    pi_build_mixed_kernel<_Float16><<<grid, 4 * mx_rows<_Float16>(), 0, stream>>>(
         Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
         n_aux, chi_re, chi_im, inv_colscale, tscale, tiles, G, g_stride, ldg);
   } else if (prec == 3) {
     taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, Mix<e4m3>::TARGET, acol, tscale);
-    pi_build_mixed_kernel<e4m3><<<grid, MX_THREADS, 0, stream>>>(
+    pi_build_mixed_kernel<e4m3><<<grid, 4 * mx_rows<e4m3>(), 0, stream>>>(
         Lf, static_cast<const unsigned char *>(Bhi), static_cast<const unsigned char *>(Blo), ldl,
         n_aux, chi_re, chi_im, inv_colscale, tscale, tiles, G, g_stride, ldg);
   } else {
-    pi_build_mixed_kernel<__bf16><<<grid, MX_THREADS, 0, stream>>>(
+    pi_build_mixed_kernel<__bf16><<<grid, 4 * mx_rows<__bf16>(), 0, stream>>>(
         Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
         n_aux, chi_re, chi_im, nullptr, nullptr, tiles, G, g_stride, ldg);
   }
