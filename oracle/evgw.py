@@ -20,9 +20,9 @@ Steps (section "GW for core levels: beyond G0W0", Eq. ev_sigma_spectral):
      b. Newton steps with the analytic derivative
           f' = 1 - d Re Sigma / dw,  d Re Sigma / dw = sum rho^2 (eta^2 - a^2) / (a^2 + eta^2)^2,
           a = w - e_m + s_m Omega,
-        from the bracket's midpoint, each replaced by the midpoint when it
-        leaves the (shrinking) bracket, until |Delta E| < tol_newton (more than
-        max_newton steps flag the state);
+        from the bracket end with the smaller |f|, each replaced by the
+        bracket's midpoint when it leaves the (shrinking) bracket, until
+        |Delta E| < tol_newton (more than max_newton steps flag the state);
    e^(k+1) = the roots; the iteration stops when max_n |e^(k+1)_n - e^(k)_n| < tol_outer.
    Plain Newton from E0 cycles for states whose root lies next to a pole of
    Sigma (virtual levels with corrections of ~10 eV on the synthetic inputs); the
@@ -87,24 +87,30 @@ def qp_root(fun, E0, eta, tol, max_steps):
     """Step 3 for one state: bracket from E0, then safeguarded Newton.
     fun(E) -> (f, f').  Returns (root, Newton steps) with steps = -1 when
     max_steps did not reach |Delta E| < tol."""
-    f0, _ = fun(E0)
+    f0, d0 = fun(E0)
     if f0 == 0.0:
         return E0, 0
     d = -1.0 if f0 > 0 else 1.0
-    a, fa = E0, f0
+    a, fa, da = E0, f0, d0
     h = eta
     for _ in range(1100):            # f ~ E: a sign change is reached within the double range
         b = E0 + d * h
-        fb, _ = fun(b)
+        fb, db = fun(b)
         if fb == 0.0:
             return b, 0
         if (fb > 0) != (fa > 0):
             break
-        a, fa = b, fb
+        a, fa, da = b, fb, db
         h *= 2.0
     lo, hi, flo = (a, b, fa) if a < b else (b, a, fb)
-    E = 0.5 * (lo + hi)
+    E, f, df = (a, fa, da) if abs(fa) <= abs(fb) else (b, fb, db)
     for it in range(1, max_steps + 1):
+        En = E - f / df if df != 0.0 else lo - 1.0
+        if not (lo < En < hi):
+            En = 0.5 * (lo + hi)
+        if abs(En - E) < tol:
+            return En, it
+        E = En
         f, df = fun(E)
         if f == 0.0:
             return E, it
@@ -112,12 +118,6 @@ def qp_root(fun, E0, eta, tol, max_steps):
             lo, flo = E, f
         else:
             hi = E
-        En = E - f / df if df != 0.0 else lo - 1.0
-        if not (lo < En < hi):
-            En = 0.5 * (lo + hi)
-        if abs(En - E) < tol:
-            return En, it
-        E = En
     return E, -1
 
 

@@ -9,8 +9,9 @@
 // ev_solve_kernel: one workgroup per state n solves f(E) = E - eps_n -
 // Sigma^x_n - Re Sigma^c,ev_n(E; e) + v^xc_n = 0 from E0 = e_n: points
 // E0 + d eta 2^j (d = -sign f(E0); f ~ E for large |E|) until f changes sign,
-// then Newton steps from the bracket's midpoint, each replaced by the midpoint
-// when it leaves the shrinking bracket, until |Delta E| < tol.  Every f is a
+// then Newton steps from the bracket end with the smaller |f|, each replaced by
+// the bracket's midpoint when it leaves the shrinking bracket, until
+// |Delta E| < tol.  Every f is a
 // block-wide reduction over (m, nu) in a fixed order; all threads run the same
 // scalar control flow on the broadcast result.
 #include "gwc_internal.h"
@@ -136,11 +137,10 @@ ev_solve_kernel(const double *__restrict__ r2, int n_ov, const double *__restric
   bool done = f0 == 0.0;
   if (!done) {
     const double d = f0 > 0.0 ? -1.0 : 1.0;
-    double a = E0, fa = f0, b = E0, fb = f0, h = eta;
+    double a = E0, fa = f0, da = df0, b = E0, fb = f0, db = df0, h = eta;
     for (int j = 0; j < 1100; ++j) {
       b = E0 + d * h;
-      double dfb;
-      fval(b, fb, dfb);
+      fval(b, fb, db);
       if (fb == 0.0) {
         root = b;
         done = true;
@@ -149,21 +149,16 @@ ev_solve_kernel(const double *__restrict__ r2, int n_ov, const double *__restric
       if ((fb > 0.0) != (fa > 0.0)) break;
       a = b;
       fa = fb;
+      da = db;
       h *= 2.0;
     }
     if (!done) {
       double lo, hi, flo;
       if (a < b) { lo = a; hi = b; flo = fa; } else { lo = b; hi = a; flo = fb; }
-      double E = 0.5 * (lo + hi);
+      double E, f, df;
+      if (fabs(fa) <= fabs(fb)) { E = a; f = fa; df = da; } else { E = b; f = fb; df = db; }
       nsteps = -1;
       for (int it = 1; it <= max_steps; ++it) {
-        double f, df;
-        fval(E, f, df);
-        if (f == 0.0) {
-          nsteps = it;
-          break;
-        }
-        if ((f > 0.0) == (flo > 0.0)) { lo = E; flo = f; } else { hi = E; }
         double En = df != 0.0 ? E - f / df : lo - 1.0;
         if (!(lo < En && En < hi)) En = 0.5 * (lo + hi);
         if (fabs(En - E) < tol) {
@@ -172,6 +167,12 @@ ev_solve_kernel(const double *__restrict__ r2, int n_ov, const double *__restric
           break;
         }
         E = En;
+        fval(E, f, df);
+        if (f == 0.0) {
+          nsteps = it;
+          break;
+        }
+        if ((f > 0.0) == (flo > 0.0)) { lo = E; flo = f; } else { hi = E; }
       }
       root = E;
     }
