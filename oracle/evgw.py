@@ -66,6 +66,47 @@ def moments_all(M_oo, M_ov, M_vv, XpY):
     return (rho * rho).reshape(nb, nb, -1)
 
 
+def moments_of_states(M_oo, M_ov, M_vv, XpY, states):
+    """(rho^nu_nm)^2 as r2[k][m][nu] for the listed states n = states[k] only
+    (the rows `moments_all` would hold for them), for large systems."""
+    n_aux, n_occ, n_virt = M_ov.shape
+    L = M_ov.reshape(n_aux, -1)
+    Rm = L @ XpY                                                  # [P][nu]
+    out = []
+    for n in states:
+        if n < n_occ:
+            Mn = np.concatenate([M_oo[:, n, :], M_ov[:, n, :]], axis=1)
+        else:
+            Mn = np.concatenate([M_ov[:, :, n - n_occ], M_vv[:, n - n_occ, :]], axis=1)
+        rho = np.sqrt(2.0) * (Mn.T @ Rm)
+        out.append(rho * rho)
+    return np.array(out)
+
+
+def first_iteration(eps, occ, M_oo, M_ov, M_vv, states, eta, vxc=None, max_newton=200,
+                    tol_newton=1e-10):
+    """Energies after the first iteration (e^(0) = eps in G, i.e. the G0W0
+    quasiparticle solutions found from eps by step 3) for the listed states,
+    each computed on its own: (E [len(states)], Newton steps)."""
+    eps = np.asarray(eps, dtype=float)
+    nb = eps.size
+    n_occ = int(np.sum(np.asarray(occ) > 0))
+    vxc = np.zeros(nb) if vxc is None else np.asarray(vxc, dtype=float)
+    sgn = np.where(np.arange(nb) < n_occ, 1.0, -1.0)
+    Om, XpY = AN.rpa_excitations(eps, n_occ, M_ov)
+    r2 = moments_of_states(M_oo, M_ov, M_vv, XpY, states)
+    sx = exchange_all(M_oo, M_ov)
+    E_out, steps = [], []
+    for k, n in enumerate(states):
+        def fun(E, k=k, n=n):
+            re, dre, _ = pole_sum(r2[k], eps, sgn, Om, E, eta)
+            return E - eps[n] - sx[n] - re + vxc[n], 1.0 - dre
+        E, it = qp_root(fun, eps[n], eta, tol_newton, max_newton)
+        E_out.append(E)
+        steps.append(it)
+    return np.array(E_out), np.array(steps)
+
+
 def exchange_all(M_oo, M_ov):
     """Sigma^x_n = -sum_i sum_P (M^P_ni)^2 for every state n."""
     sx_occ = -np.sum(M_oo ** 2, axis=(0, 2))

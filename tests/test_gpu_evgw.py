@@ -90,3 +90,21 @@ def test_evgw0_rejects_nonfinite_vv():
     with pytest.raises(gwc.GwcError) as ei:
         _run(s, vv)
     assert ei.value.status_name == "GWC_ERR_NONFINITE"
+
+
+def test_evgw0_c2_first_iteration_sampled():
+    """Benzene-sized system (300 states, N_ov = 5859) at the size the bench
+    times: the first iteration's energies (the G0W0 solutions from eps, each a
+    function of its own state only) of the 6 cores and a sample of valence and
+    virtual states, computed one by one by the oracle; the run converges."""
+    s = system_from_config(CONFIGS["c2"])
+    vv = vv_block(s)
+    print("case evgw0 c2 sampled", flush=True)
+    out = _run(s, vv)
+    states = [0, 1, 2, 3, 4, 5, 10, 20, 21, 60, 150, 299]
+    E, steps = EV.first_iteration(s.eps, s.occ, s.M_oo, s.M_ov, vv, states, s.eta)
+    rel = np.max(np.abs(out["e_first"][states] - E)) / np.max(np.abs(E))
+    print(f"  e_first sampled rel {rel:.2e}; outer {int(out['outer'][0])}", flush=True)
+    assert np.all(steps >= 0)
+    assert rel <= TOL
+    assert int(out["outer"][0]) > 0 and np.all(out["newton"] >= 0)

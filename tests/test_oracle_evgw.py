@@ -116,3 +116,15 @@ def test_moments_all_match_single_state_moments(n):
         ref = (np.sqrt(2.0) * (Bn.T @ s.M_ov.reshape(s.n_aux, -1)) @ XpY) ** 2
     assert np.allclose(r2[n], ref, rtol=1e-12, atol=1e-18)
     assert np.allclose(r2[:, n, :], r2[n], rtol=1e-12, atol=1e-18)   # symmetric in (n, m)
+
+
+def test_first_iteration_by_state_equals_full_run():
+    """`first_iteration` (one state at a time, for large systems) reproduces the
+    first iteration of the full run."""
+    s = system_from_config(small_config(n_occ=5, n_virt=14, n_aux=40, n_core=2, seed=23))
+    vv = vv_block(s)
+    full = EV.evgw0(s.eps, s.occ, s.M_oo, s.M_ov, vv, s.core_idx, s.omega_real, s.eta)
+    states = [0, 1, 4, 7, 18]
+    E, steps = EV.first_iteration(s.eps, s.occ, s.M_oo, s.M_ov, vv, states, s.eta)
+    assert np.all(steps >= 0)
+    assert np.allclose(E, full["e_first"][states], rtol=1e-13, atol=0)
