@@ -6,9 +6,10 @@
 // Im Sigma.  The server owns n_slots worker threads, each with its own HIP
 // stream.  A free worker takes the oldest queued request as soon as the
 // request's predicted device footprint fits in the HBM budget next to the
-// requests already running, so requests arriving while others are on the GPU
-// start as slots and memory free up, and the kernels of concurrent requests
-// (molecules of different sizes) overlap on the device.  Every request's work
+// requests already running (gwc::Admission, gwc_admission.h), so requests
+// arriving while others are on the GPU start as slots and memory free up, and
+// the kernels of concurrent requests (molecules of different sizes) overlap on
+// the device.  Every request's work
 // is decomposed the same way whatever runs beside it (the batch sizes depend
 // only on the request and the server's per-request batch budget), so its
 // results do not depend on the mix.
@@ -22,6 +23,7 @@
 #include <vector>
 
 #include "gwc.h"
+#include "gwc_admission.h"
 #include "gwc_host.h"
 
 gwc::ResidentSystem *gwc_handle_system(gwc_system_handle h);
@@ -56,15 +58,11 @@ struct gwc_server_s {
   size_t budget = 0, batch_bytes = 0;
   int device = 0;
   Clock::time_point t0;
-  std::mutex mu;
+  std::unique_ptr<gwc::Admission<Request>> adm;
+  std::mutex mu;  // request table and completion flags
   std::condition_variable cv;
-  std::deque<Request *> queue;
   std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
-  size_t in_use = 0, peak_in_use = 0;
-  int active = 0, peak_active = 0;
   int64_t next_id = 1;
-  long long completed = 0;
-  bool stop = false;
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
 
@@ -127,32 +125,20 @@ void worker_loop(gwc_server_s *srv, int slot) {
   (void)hipSetDevice(srv->device);
   hipStream_t s = srv->streams[slot];
   for (;;) {
-    Request *r = nullptr;
+    size_t footprint = 0;
+    Request *r = srv->adm->acquire(footprint);
+    if (!r) return;
     {
-      std::unique_lock<std::mutex> lock(srv->mu);
-      srv->cv.wait(lock, [&] {
-        if (srv->stop) return true;
-        return !srv->queue.empty() && srv->in_use + srv->queue.front()->footprint <= srv->budget;
-      });
-      if (srv->stop && srv->queue.empty()) return;
-      if (srv->queue.empty() || srv->in_use + srv->queue.front()->footprint > srv->budget) continue;
-      r = srv->queue.front();
-      srv->queue.pop_front();
-      srv->in_use += r->footprint;
-      srv->peak_in_use = std::max(srv->peak_in_use, srv->in_use);
-      srv->active += 1;
-      srv->peak_active = std::max(srv->peak_active, srv->active);
+      std::lock_guard<std::mutex> lock(srv->mu);
       r->t_start = srv->now();
     }
     execute(srv, r, s);
     {
       std::lock_guard<std::mutex> lock(srv->mu);
-      srv->in_use -= r->footprint;
-      srv->active -= 1;
-      srv->completed += 1;
       r->t_end = srv->now();
       r->done = true;
     }
+    srv->adm->release(footprint);
     srv->cv.notify_all();
   }
 }
@@ -185,6 +171,7 @@ int gwc_server_create(const gwc_server_config *cfg, gwc_server_handle *out) {
     srv->n_slots = cfg->n_slots;
     srv->budget = (size_t)cfg->hbm_budget_bytes;
     srv->batch_bytes = cfg->batch_bytes > 0 ? (size_t)cfg->batch_bytes : srv->budget / 4;
+    srv->adm.reset(new gwc::Admission<Request>(srv->budget));
     srv->t0 = Clock::now();
     if (hipGetDevice(&srv->device) != hipSuccess) {
       (void)hipGetLastError();
@@ -241,14 +228,15 @@ int gwc_server_submit(gwc_server_handle srv, const gwc_request *rq, int64_t *tic
     if (r->footprint > srv->budget)
       gwc::fail(GWC_ERR_OUT_OF_MEMORY, "request footprint %zu bytes exceeds the budget %zu", r->footprint, srv->budget);
     {
+      // table entry and queue position under one lock: tickets follow queue order
       std::lock_guard<std::mutex> lock(srv->mu);
       r->id = srv->next_id++;
       r->t_submit = srv->now();
       *ticket = r->id;
-      srv->queue.push_back(r.get());
-      srv->reqs.emplace(r->id, std::move(r));
+      Request *rp = r.get();
+      srv->reqs.emplace(rp->id, std::move(r));
+      (void)srv->adm->submit(rp, rp->footprint);  // fits: checked above
     }
-    srv->cv.notify_all();
     return GWC_OK;
   });
 }
@@ -288,13 +276,13 @@ int gwc_server_wait(gwc_server_handle srv, int64_t ticket, gwc_request_result *r
 int gwc_server_stats(gwc_server_handle srv, gwc_server_stats_t *st) {
   return guarded_server([&] {
     if (!srv || !st) gwc::fail(GWC_ERR_INVALID_ARG, "NULL server or stats");
-    std::lock_guard<std::mutex> lock(srv->mu);
-    st->queued = (int32_t)srv->queue.size();
-    st->active = srv->active;
-    st->peak_active = srv->peak_active;
-    st->completed = srv->completed;
-    st->in_use_bytes = (double)srv->in_use;
-    st->peak_in_use_bytes = (double)srv->peak_in_use;
+    const auto a = srv->adm->stats();
+    st->queued = (int32_t)a.queued;
+    st->active = a.active;
+    st->peak_active = a.peak_active;
+    st->completed = a.completed;
+    st->in_use_bytes = (double)a.in_use;
+    st->peak_in_use_bytes = (double)a.peak_in_use;
     st->budget_bytes = (double)srv->budget;
     return GWC_OK;
   });
@@ -303,11 +291,7 @@ int gwc_server_stats(gwc_server_handle srv, gwc_server_stats_t *st) {
 int gwc_server_destroy(gwc_server_handle srv) {
   return guarded_server([&] {
     if (!srv) gwc::fail(GWC_ERR_INVALID_ARG, "NULL server");
-    {
-      std::lock_guard<std::mutex> lock(srv->mu);
-      srv->stop = true;
-    }
-    srv->cv.notify_all();
+    srv->adm->stop();
     for (auto &t : srv->workers) t.join();
     for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
     delete srv;
