@@ -35,6 +35,24 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pi_build_f64_c2_traffic.json")
 PI_SOURCE = os.path.join(ROOT, "paper_2412_17132_amd", "csrc", "kernels_pi.hip")
 
 
+def emit(record: dict, jsonl=None) -> None:
+    """Prints the result line and, with --jsonl, appends it (with a UTC time stamp
+    and the git revision when available) as one line of a JSON-lines log."""
+    print(json.dumps(record), flush=True)
+    if jsonl:
+        import datetime
+        import subprocess
+        rec = dict(record)
+        rec["logged_utc"] = datetime.datetime.now(datetime.timezone.utc).isoformat(timespec="seconds")
+        try:
+            rec["git_rev"] = subprocess.run(["git", "-C", ROOT, "rev-parse", "--short", "HEAD"],
+                                            capture_output=True, text=True, timeout=10).stdout.strip() or None
+        except (OSError, subprocess.SubprocessError):
+            rec["git_rev"] = None
+        with open(jsonl, "a") as f:
+            f.write(json.dumps(rec) + "\n")
+
+
 def _sha(path):
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
@@ -249,7 +267,7 @@ def sampled_main(args):
         "kernels": {"pi_build": {"ms": pi["total_ms"], "launches": pi["launches"], "tflops": pi_tf},
                     "lu_bordered": {"ms": lu["total_ms"], "launches": lu["launches"], "tflops": lu_tf}},
     }
-    print(json.dumps(line), flush=True)
+    emit(line, args.jsonl)
 
 
 def _satellites(w, A, e_qp, Z, eta, min_sep_ev=0.5, rel_height=0.05):
@@ -368,7 +386,7 @@ def serve_main(args):
                     "peak_in_use_gb": st["peak_in_use_bytes"] / 2 ** 30,
                     "mean_nbasis": float(np.mean(nbs))},
     }
-    print(json.dumps(line), flush=True)
+    emit(line, args.jsonl)
 
 
 def main():
@@ -408,6 +426,9 @@ def main():
     ap.add_argument("--serve-max-nbasis", type=int, default=1100)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=96.0)
+    ap.add_argument("--jsonl", default=None,
+                    help="also append the result line (plus time stamp and git revision) to this "
+                         "JSON-lines file")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -693,7 +714,7 @@ def main():
             res["roofline"]["frac_of_measured"] = achieved / pk["fp64_mfma_tflops"]
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(s, args.mode, n_tasks / n_core, args.cpu_tasks)
-    print(json.dumps(res), flush=True)
+    emit(res, args.jsonl)
 
 
 if __name__ == "__main__":

@@ -26,3 +26,17 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_jsonl_record_is_appended(tmp_path, capsys):
+    """--jsonl appends each result line, time-stamped, to a JSON-lines log."""
+    import json
+    import bench
+    log = tmp_path / "runs.jsonl"
+    bench.emit({"metric": "m", "value": 1.0}, str(log))
+    bench.emit({"metric": "m", "value": 2.0}, str(log))
+    out = capsys.readouterr().out.strip().splitlines()
+    assert [json.loads(x)["value"] for x in out] == [1.0, 2.0]
+    recs = [json.loads(x) for x in log.read_text().splitlines()]
+    assert [r["value"] for r in recs] == [1.0, 2.0]
+    assert all("logged_utc" in r and "git_rev" in r for r in recs)
