@@ -25,10 +25,10 @@
 //   S  one workgroup per (matrix, 16 columns): applies the row moves and forms
 //      U12 = L11^-1 A12 on MFMA;
 //   G  one workgroup per (matrix, 64 x 64 tile): A22 -= L21 U12 on MFMA (the
-//      complex product as four real products), tiles of a matrix kept on one
+//      complex product as three real products), tiles of a matrix kept on one
 //      XCD so its L21 / U12 panels stay in that L2.
-// Two panels share one trailing update with K = 128 while at least 128 pivot
-// columns remain.
+// Up to LU_GROUP panels share one trailing update (K = 64 LU_GROUP) while at
+// least two whole panels remain.
 #include "gwc_internal.h"
 
 namespace gwc {
@@ -41,6 +41,7 @@ constexpr int PNW = PT / 64;
 constexpr int MAX_MOVES = 2 * NBO;
 constexpr int SW = 16;                      // trailing columns per swap/U12 workgroup
 constexpr int NXCD = 8;
+constexpr int LU_GROUP = 3;                 // panels per wide trailing update
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -414,9 +415,9 @@ lu_linv_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, int 
 // ===========================================================================
 // S: row moves on columns [c_start, c_end) (16 per workgroup, 4 waves of 16
 // rows each); with u12, then U12 = L11^-1 A12 for the panel rows K0..K0+64,
-// after subtracting the previous 64-column block's contribution
-// A[K0.., kpre..kpre+64] A[kpre..kpre+64, ..] when kpre >= 0 (the second
-// panel of a 128-column step, whose rows the wide trailing update skips).
+// after subtracting the contribution of the earlier panels of its group
+// A[K0.., kpre..K0] A[kpre..K0, ..] when kpre >= 0 (a later panel of a
+// grouped step, whose rows the wide trailing update skips).
 __global__ void __launch_bounds__(256)
 lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0, int F,
                    int nchunks, int c_start, int c_end, int kpre, int u12,
@@ -454,8 +455,9 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
   if (kpre >= 0) {
     d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
     const int arow = K0 + 16 * wave + li;
+    const int kplen = K0 - kpre;
 #pragma unroll 4
-    for (int kk = 0; kk < NBO; kk += 4) {
+    for (int kk = 0; kk < kplen; kk += 4) {
       const int k = kpre + kk + lk;
       const double2 a = (16 * wave + li < kbo) ? A[(long long)arow * ldg + k] : make_double2(0.0, 0.0);
       const double2 b = (li < cw) ? A[(long long)k * ldg + c0 + li] : make_double2(0.0, 0.0);
@@ -491,12 +493,14 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
 
 // ===========================================================================
 // G: trailing update A[rows, cols] -= A[rows, K] A[K, cols] over the K range
-// [kstart, kstart + klen) (64, or 128 for a two-panel step), one 64 x 64 tile
+// [kstart, kstart + klen) (a multiple of 64 up to 64 LU_GROUP, or the ragged
+// last panel), one 64 x 64 tile
 // per workgroup on an mt_r x mt_c grid from (row0, col0), columns below col_end
 // only (a range may end inside a tile); the MFMA operands
 // come straight from memory (the panels of one matrix are shared in its XCD's
-// L2), so the K loop has no barriers.
-__global__ void __launch_bounds__(256, 4)
+// L2), so the K loop has no barriers.  The operands of the next k step are
+// loaded into a second register set while the MFMAs of the current one run.
+__global__ void __launch_bounds__(256, 3)
 lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int F, int row0,
                    int col0, int col_end, int mt_r, int mt_c, int kstart, int klen) {
   int f, tile;
@@ -522,20 +526,7 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
       p2[a][b] = d4{0.0, 0.0, 0.0, 0.0};
       p3[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     }
-#pragma unroll 4
-  for (int kk = 0; kk < klen; kk += 4) {
-    const int k = kk + lk;
-    double2 lv[2], uv[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int row = ra + wr + 16 * a + li;
-      lv[a] = (row < n && k < klen) ? A[(long long)row * ldg + kstart + k] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int col = ca + wc + 16 * b + li;
-      uv[b] = (k < klen && col < col_end) ? A[(long long)(kstart + k) * ldg + col] : make_double2(0.0, 0.0);
-    }
+  auto mfmas = [&](const double2 (&lv)[2], const double2 (&uv)[2]) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const double ls = lv[a].x + lv[a].y;
@@ -547,20 +538,75 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
         p3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ls, us, p3[a][b], 0, 0, 0);
       }
     }
+  };
+
+  // Whole steps of 4 k: rows >= n and columns >= col_end only feed outputs
+  // that are never stored, so their operands come unmasked from a clamped,
+  // in-bounds row or column.
+  const double2 *lrow[2], *ucol[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+    lrow[a] = A + (long long)min(ra + wr + 16 * a + li, n - 1) * ldg + kstart + lk;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+    ucol[b] = A + (long long)(kstart + lk) * ldg + min(ca + wc + 16 * b + li, col_end - 1);
+  const long long ustep = 4LL * ldg;
+  auto load_ops = [&](int kk, double2 (&lv)[2], double2 (&uv)[2]) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) lv[a] = lrow[a][kk];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) uv[b] = ucol[b][(kk >> 2) * ustep];
+  };
+  const int klen4 = klen & ~3;
+  if (klen4 > 0) {
+    double2 la[2], ua[2], lb[2], ub[2];
+    load_ops(0, la, ua);
+    for (int kk = 0; kk < klen4; kk += 8) {
+      load_ops(min(kk + 4, klen4 - 4), lb, ub);
+      __builtin_amdgcn_sched_barrier(0);  // keep the next loads ahead of these MFMAs
+      mfmas(la, ua);
+      if (kk + 4 >= klen4) break;
+      load_ops(min(kk + 8, klen4 - 4), la, ua);
+      __builtin_amdgcn_sched_barrier(0);
+      mfmas(lb, ub);
+    }
   }
+  if (klen4 < klen) {
+    // ragged end of the K range: lanes with k >= klen contribute zero
+    const int k = klen4 + lk;
+    double2 lv[2], uv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int row = ra + wr + 16 * a + li;
+      lv[a] = (k < klen && row < n) ? A[(long long)row * ldg + kstart + k] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = ca + wc + 16 * b + li;
+      uv[b] = (k < klen && col < col_end) ? A[(long long)(kstart + k) * ldg + col]
+                                          : make_double2(0.0, 0.0);
+    }
+    mfmas(lv, uv);
+  }
+
+  // each 16 x 16 block: its four values per lane are all loaded before any is
+  // stored (one memory round trip per block)
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const int col = ca + wc + 16 * b + li;
+      const int col = ca + wc + 16 * b + li, colc = min(col, col_end - 1);
+      double2 x[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        x[r] = A[(long long)min(ra + wr + 16 * a + 4 * r + lk, n - 1) * ldg + colc];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = ra + wr + 16 * a + 4 * r + lk;
-        if (row < n && col < col_end) {
-          double2 &x = A[(long long)row * ldg + col];
-          const double q1 = p1[a][b][r], q2 = p2[a][b][r];
-          x = make_double2(x.x - (q1 - q2), x.y - (p3[a][b][r] - q1 - q2));
-        }
+        const double q1 = p1[a][b][r], q2 = p2[a][b][r];
+        if (row < n && col < col_end)
+          A[(long long)row * ldg + col] =
+              make_double2(x[r].x - (q1 - q2), x[r].y - (p3[a][b][r] - q1 - q2));
       }
     }
 }
@@ -654,17 +700,23 @@ hipError_t launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, in
   const LuLaunch L{G, g_stride, ldg, N, R, F, (F + NXCD - 1) / NXCD, piv, moves, status, linv, stream};
   int K0 = 0;
   while (K0 < N) {
-    if (N - K0 >= 2 * NBO) {
-      // two 64-column panels a, b, then one trailing update with K = 128:
-      // the A22 block streams through memory once per 128 columns
-      const int a = K0, b = K0 + NBO, e = K0 + 2 * NBO;
-      L.panel(a);
-      L.swap_u12(a, b, n, -1, 1);           // a's moves and U rows on every column right of it
-      L.trailing(b, b, b + NBO, a, NBO);    // a's update of panel b only
-      L.panel(b);
-      L.swap_u12(b, a, b, -1, 0);           // b's moves on a's L columns
-      L.swap_u12(b, e, n, a, 1);            // b's moves, a's update of rows b..e, b's U rows
-      L.trailing(e, e, n, a, 2 * NBO);      // rows, columns >= e with K = [a, e)
+    const int g = min(LU_GROUP, (N - K0) / NBO);
+    if (g >= 2) {
+      // g whole panels, then one trailing update with K = 64 g: the A22 block
+      // streams through memory once per 64 g columns.  Panel p first receives
+      // the updates of the group's earlier panels on its own columns; after
+      // it is factored, its row moves reach the group's earlier L columns, and
+      // its U rows (less the earlier panels' contribution) every column to its
+      // right.
+      const int a = K0, e = K0 + g * NBO;
+      for (int p = 0; p < g; ++p) {
+        const int b = a + p * NBO;
+        if (p > 0) L.trailing(b, b, b + NBO, a, p * NBO);
+        L.panel(b);
+        if (p > 0) L.swap_u12(b, a, b, -1, 0);
+        L.swap_u12(b, b + NBO, n, p > 0 ? a : -1, 1);
+      }
+      L.trailing(e, e, n, a, g * NBO);
       K0 = e;
     } else {
       const int kend = min(K0 + NBO, N);
