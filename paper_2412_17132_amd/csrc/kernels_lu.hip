@@ -84,6 +84,7 @@ struct PanelShared {
   double2 prow[WMAX];
   double2 xbuf[WMAX];
   double2 lbb[WMAX][WMAX + 1];
+  double2 lpre[WMAX][WMAX + 1];  // an odd block's rows of the even block's L
   int pslot[NBO];
   struct {
     struct {
@@ -101,15 +102,18 @@ struct PanelShared {
 //   2. the block is stored, and its interchanges are applied to the panel
 //      columns left and right of it in one pass through LDS (net row moves);
 //   3. the block's U rows on the columns to its right are solved with its unit
-//      lower diagonal block (one thread per column, in registers);
-//   4. every thread applies the rank-W update to its own rows of those
-//      columns, with the block's L values still in its registers.
+//      lower diagonal block (one thread per column, U rows kept in LDS);
+//   4. the rows below are updated on MFMA stripes.  Blocks go in pairs: an
+//      even block updates only the next block's columns, the odd block then
+//      applies both blocks' rank-2W update to every column to its right, so
+//      the rest of the panel is read and written once per pair instead of
+//      once per block.
 template <int RPT, int W, int WPE>
 __global__ void __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(WPE)))
 lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0,
                 int *__restrict__ piv_g, int *__restrict__ moves_g, double2 *__restrict__ linv_g,
                 int *__restrict__ status) {
-  static_assert(W <= WMAX, "column block wider than the shared buffers");
+  static_assert(2 * W <= WMAX, "a pair of column blocks wider than the shared buffers");
   __shared__ PanelShared sh;
   const int f = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -264,18 +268,39 @@ lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, in
     }
     __syncthreads();
     if (ke < kend) {
+      // Blocks go in pairs (even, odd) by (k0 - K0) / W.  After an even block
+      // only the next block's W columns are updated; after the odd block one
+      // rank-(W + kb) update reaches every column to its right, so the rest of
+      // the panel streams through memory once per pair.  The U rows of both
+      // blocks stay in the U buffer, columns counted from the pair's base (the
+      // even block's ke): the even block's in rows 0..W, the odd block's in
+      // rows W..W+kb.
+      const bool odd = (((k0 - K0) / W) & 1) != 0;
+      const int base = odd ? k0 : ke, urow = odd ? W : 0;
       // 3. U rows k0..ke of columns ke..kend: unit lower solve with the
-      //    diagonal block (rows k0..ke are slot 0 of threads k0-K0 .. ke-K0)
+      //    diagonal block (rows k0..ke are slot 0 of threads k0-K0 .. ke-K0),
+      //    for an odd block after subtracting the even block's contribution
+      //    L[k0..ke, k0-W..k0] U_even (its update of these rows was deferred)
       if (tid >= k0 - K0 && tid < ke - K0) {
         const int i = tid - (k0 - K0);
 #pragma unroll
         for (int t = 0; t < W; ++t) sh.lbb[i][t] = v[0][t];
       }
+      if (odd)
+        for (int idx = tid; idx < kb * W; idx += PT) {
+          const int i = idx / W, t = idx - i * W;
+          sh.lpre[i][t] = A[(long long)(k0 + i) * ldg + k0 - W + t];
+        }
       __syncthreads();
       // one thread per column; the solved rows accumulate in the U buffer
       for (int c = ke + tid; c < kend; c += PT) {
-        double2 *uc = &sh.u.blk.U[0][c - ke];
-        for (int i = 0; i < kb; ++i) uc[i * NBO] = A[(long long)(k0 + i) * ldg + c];
+        double2 *uc = &sh.u.blk.U[urow][c - base];
+        for (int i = 0; i < kb; ++i) {
+          double2 x = A[(long long)(k0 + i) * ldg + c];
+          if (odd)
+            for (int t = 0; t < W; ++t) x = csub(x, cmul(sh.lpre[i][t], sh.u.blk.U[t][c - base]));
+          uc[i * NBO] = x;
+        }
 #pragma unroll 1
         for (int i = 1; i < kb; ++i) {
           double2 x = uc[i * NBO];
@@ -285,12 +310,16 @@ lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, in
         for (int i = 0; i < kb; ++i) A[(long long)(k0 + i) * ldg + c] = uc[i * NBO];
       }
       __syncthreads();
-      // 4. rank-kb update of rows ke..n on columns ke..kend (at most 4 tiles of
-      //    16 columns) on MFMA, without barriers: each wave takes 16-row
-      //    stripes; L from the block just stored, U from LDS.  The MFMA
-      //    layouts: A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16].
+      // 4. update of rows ke..n on columns ke..cend (at most 4 tiles of 16
+      //    columns) with the K range kbeg..kbeg+klen on MFMA, without
+      //    barriers: each wave takes 16-row stripes; L from the stored
+      //    blocks, U from LDS (columns past cend read a clamped U column and
+      //    are not stored).  The MFMA layouts: A[l%16][l/16], B[l/16][l%16],
+      //    D[4r + l/16][l%16].
       const int li = lane & 15, lk = lane >> 4;
-      const int nct = (kend - ke + 15) / 16;
+      const int cend = odd ? kend : min(ke + W, kend);
+      const int kbeg = odd ? k0 - W : k0, klen = odd ? W + kb : kb, uoff = ke - base;
+      const int nct = (cend - ke + 15) / 16;
 #pragma unroll 1
       for (int r0 = ke + 16 * wave; r0 < n; r0 += 16 * PNW) {
         d4 cre[4], cim[4];
@@ -301,22 +330,23 @@ lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, in
           for (int r = 0; r < 4; ++r) {
             const int row = r0 + 4 * r + lk;
             double2 x = make_double2(0.0, 0.0);
-            if (ct < nct && row < n && col < kend) x = A[(long long)row * ldg + col];
+            if (ct < nct && row < n && col < cend) x = A[(long long)row * ldg + col];
             cre[ct][r] = x.x;
             cim[ct][r] = x.y;
           }
         }
 #pragma unroll
-        for (int kk = 0; kk < W; kk += 4) {
-          if (kk < kb) {
+        for (int kk = 0; kk < 2 * W; kk += 4) {
+          if (kk < klen) {
             const int row = r0 + li, k = kk + lk;
-            const double2 lv = (row < n && k < kb) ? A[(long long)row * ldg + k0 + k]
-                                                   : make_double2(0.0, 0.0);
+            const double2 lv = (row < n && k < klen) ? A[(long long)row * ldg + kbeg + k]
+                                                     : make_double2(0.0, 0.0);
             const double ar = -lv.x, ai = -lv.y;
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) {
               if (ct < nct) {
-                const double2 uv = k < kb ? sh.u.blk.U[k][16 * ct + li] : make_double2(0.0, 0.0);
+                const double2 uv = k < klen ? sh.u.blk.U[k][min(uoff + 16 * ct + li, NBO - 1)]
+                                            : make_double2(0.0, 0.0);
                 cre[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.x, cre[ct], 0, 0, 0);
                 cre[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, uv.y, cre[ct], 0, 0, 0);
                 cim[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, uv.y, cim[ct], 0, 0, 0);
@@ -331,7 +361,7 @@ lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, in
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = r0 + 4 * r + lk;
-            if (ct < nct && row < n && col < kend)
+            if (ct < nct && row < n && col < cend)
               A[(long long)row * ldg + col] = make_double2(cre[ct][r], cim[ct][r]);
           }
         }
@@ -657,9 +687,9 @@ struct LuLaunch {
 
   void panel(int K0) const {
     const int rpt = (N + R + PT - 1) / PT;
-    // register block v[RPT][W] kept at <= 128 VGPRs
-    if (rpt <= 1) launch_panel<1, 8, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 2) launch_panel<2, 8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    // register block v[RPT][W] kept at <= 128 VGPRs; up to 512 rows take the
+    // two-row form too (the one-row form spills its update accumulators)
+    if (rpt <= 2) launch_panel<2, 8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
     else if (rpt <= 3) launch_panel<3, 8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
     else if (rpt <= 4) launch_panel<4, 8, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
     else if (rpt <= 6) launch_panel<6, 4, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
