@@ -453,7 +453,7 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
                    int nchunks, int c_start, int c_end, int kpre, int u12,
                    const int *__restrict__ moves_g, const double2 *__restrict__ linv_g) {
   __shared__ int mv[1 + 2 * MAX_MOVES];
-  __shared__ double2 val[MAX_MOVES][SW + 1];
+  __shared__ double2 val[NBO][SW + 1];
   int f, chunk;
   if (!xcd_map(blockIdx.x, nchunks, F, f, chunk)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -465,15 +465,22 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
   const int *m = moves_g + (long long)f * (1 + 2 * MAX_MOVES);
   for (int i = tid; i < 1 + 2 * MAX_MOVES; i += 256) mv[i] = m[i];
   __syncthreads();
+  // the moves go through registers: every source is read before any
+  // destination is written (a row can be both)
   const int cnt = mv[0];
-  for (int idx = tid; idx < cnt * SW; idx += 256) {
-    const int i = idx / SW, j = idx - i * SW;
-    val[i][j] = (j < cw) ? A[(long long)mv[2 + 2 * i] * ldg + c0 + j] : make_double2(0.0, 0.0);
+  constexpr int MPT = MAX_MOVES * SW / 256;
+  double2 moved[MPT];
+#pragma unroll
+  for (int q = 0; q < MPT; ++q) {
+    const int idx = tid + 256 * q, i = idx / SW, j = idx - i * SW;
+    moved[q] = (i < cnt && j < cw) ? A[(long long)mv[2 + 2 * i] * ldg + c0 + j]
+                                   : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  for (int idx = tid; idx < cnt * SW; idx += 256) {
-    const int i = idx / SW, j = idx - i * SW;
-    if (j < cw) A[(long long)mv[1 + 2 * i] * ldg + c0 + j] = val[i][j];
+#pragma unroll
+  for (int q = 0; q < MPT; ++q) {
+    const int idx = tid + 256 * q, i = idx / SW, j = idx - i * SW;
+    if (i < cnt && j < cw) A[(long long)mv[1 + 2 * i] * ldg + c0 + j] = moved[q];
   }
   if (!u12) return;
   __syncthreads();
