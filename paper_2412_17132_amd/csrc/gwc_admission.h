@@ -38,7 +38,9 @@ class Admission {
 
   // Blocks until the oldest request fits (returns it and its footprint, now
   // counted as in use) or the server stops with an empty queue (nullptr).
-  Item *acquire(size_t &footprint) {
+  // `ticket`, when given, receives the request's admission number (0, 1, ...
+  // in the order requests are handed out).
+  Item *acquire(size_t &footprint, long long *ticket = nullptr) {
     std::unique_lock<std::mutex> lock(mu_);
     cv_.wait(lock, [&] { return fits_locked() || (stop_ && queue_.empty()); });
     if (queue_.empty()) return nullptr;
@@ -49,6 +51,8 @@ class Admission {
     active_ += 1;
     peak_active_ = std::max(peak_active_, active_);
     footprint = e.footprint;
+    if (ticket) *ticket = admitted_;
+    admitted_ += 1;
     return e.item;
   }
 
@@ -96,7 +100,7 @@ class Admission {
   std::deque<Entry> queue_;
   size_t in_use_ = 0, peak_in_use_ = 0;
   int active_ = 0, peak_active_ = 0;
-  long long completed_ = 0;
+  long long completed_ = 0, admitted_ = 0;
   bool stop_ = false;
 };
 

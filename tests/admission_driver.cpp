@@ -123,15 +123,18 @@ void head_of_line() {
   b.id = 1; b.footprint = 50;
   c.id = 2; c.footprint = 10;
   std::atomic<int> started{0};
-  std::vector<int> order(3, -1);
+  std::vector<int> order(3, -1);  // by admission ticket (taken under the policy's lock)
   std::vector<std::thread> ws;
   for (int k = 0; k < 3; ++k)
     ws.emplace_back([&] {
       for (;;) {
         size_t fp = 0;
-        Item *it = adm.acquire(fp);
+        long long ticket = -1;
+        Item *it = adm.acquire(fp, &ticket);
         if (!it) return;
-        order[started.fetch_add(1)] = it->id;
+        CHECK(ticket >= 0 && ticket < 3);
+        order[ticket] = it->id;
+        started.fetch_add(1);
         while (it->hold.load()) sleep_us(100);
         adm.release(fp);
       }
