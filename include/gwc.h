@@ -348,8 +348,9 @@ typedef struct {
  * every state's quasiparticle equation (Eq. quasiparticle_equation)
  *   E = eps_n + Sigma^x_n + Re Sigma^c,ev_n(E; e^(k)) - v^xc_n
  * is solved from E0 = e^(k)_n (e^(0) = eps): points E0 + d eta 2^j, d = -sign f(E0),
- * until f changes sign, then Newton steps (analytic derivative) from the bracket's
- * midpoint, each replaced by the midpoint when it leaves the shrinking bracket;
+ * until f changes sign, then Newton steps (analytic derivative) from the bracket end
+ * with the smaller |f|, each replaced by the Illinois false-position point of the
+ * shrinking bracket when it leaves it (the midpoint if that point rounds onto an end);
  * e^(k+1) = the roots, until max_n |e^(k+1)_n - e^(k)_n| < tol_outer.
  * Device memory ~ 8 (n_basis^2 (n_ov + n_aux) + n_ov^2 + 3 n_aux n_ov) bytes,
  * n_ov = n_occ * n_virt <= 65536.  Non-convergence is reported in `outer` and

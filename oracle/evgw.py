@@ -21,7 +21,8 @@ Steps (section "GW for core levels: beyond G0W0", Eq. ev_sigma_spectral):
           f' = 1 - d Re Sigma / dw,  d Re Sigma / dw = sum rho^2 (eta^2 - a^2) / (a^2 + eta^2)^2,
           a = w - e_m + s_m Omega,
         from the bracket end with the smaller |f|, each replaced by the
-        bracket's midpoint when it leaves the (shrinking) bracket, until
+        Illinois false-position point of the (shrinking) bracket when it leaves
+        it (the midpoint if that point rounds onto an end), until
         |Delta E| < tol_newton (more than max_newton steps flag the state);
    e^(k+1) = the roots; the iteration stops when max_n |e^(k+1)_n - e^(k)_n| < tol_outer.
    Plain Newton from E0 cycles for states whose root lies next to a pole of
@@ -125,7 +126,8 @@ def pole_sum(r2n, e, sgn, Om, w, eta):
 
 
 def qp_root(fun, E0, eta, tol, max_steps):
-    """Step 3 for one state: bracket from E0, then safeguarded Newton.
+    """Step 3 for one state: bracket from E0, then safeguarded Newton (a step
+    that leaves the bracket is replaced by the Illinois false-position point).
     fun(E) -> (f, f').  Returns (root, Newton steps) with steps = -1 when
     max_steps did not reach |Delta E| < tol."""
     f0, d0 = fun(E0)
@@ -143,12 +145,17 @@ def qp_root(fun, E0, eta, tol, max_steps):
             break
         a, fa, da = b, fb, db
         h *= 2.0
-    lo, hi, flo = (a, b, fa) if a < b else (b, a, fb)
+    lo, hi, flo, fhi = (a, b, fa, fb) if a < b else (b, a, fb, fa)
     E, f, df = (a, fa, da) if abs(fa) <= abs(fb) else (b, fb, db)
+    kept = 0                         # -1: the last update moved lo, +1: it moved hi
     for it in range(1, max_steps + 1):
         En = E - f / df if df != 0.0 else lo - 1.0
         if not (lo < En < hi):
-            En = 0.5 * (lo + hi)
+            # false position on the bracket, the Illinois way: the f of an end
+            # kept through two updates in a row is halved
+            En = (lo * fhi - hi * flo) / (fhi - flo)
+            if not (lo < En < hi):
+                En = 0.5 * (lo + hi)
         if abs(En - E) < tol:
             return En, it
         E = En
@@ -157,8 +164,14 @@ def qp_root(fun, E0, eta, tol, max_steps):
             return E, it
         if (f > 0) == (flo > 0):
             lo, flo = E, f
+            if kept == -1:
+                fhi *= 0.5
+            kept = -1
         else:
-            hi = E
+            hi, fhi = E, f
+            if kept == 1:
+                flo *= 0.5
+            kept = 1
     return E, -1
 
 

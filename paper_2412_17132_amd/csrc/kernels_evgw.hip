@@ -10,8 +10,8 @@
 // Sigma^x_n - Re Sigma^c,ev_n(E; e) + v^xc_n = 0 from E0 = e_n: points
 // E0 + d eta 2^j (d = -sign f(E0); f ~ E for large |E|) until f changes sign,
 // then Newton steps from the bracket end with the smaller |f|, each replaced by
-// the bracket's midpoint when it leaves the shrinking bracket, until
-// |Delta E| < tol.  Every f is a
+// the Illinois false-position point of the shrinking bracket (the midpoint if
+// that rounds onto an end) when it leaves the bracket, until |Delta E| < tol.  Every f is a
 // block-wide reduction over (m, nu) in a fixed order; all threads run the same
 // scalar control flow on the broadcast result.
 #include "gwc_internal.h"
@@ -153,14 +153,20 @@ ev_solve_kernel(const double *__restrict__ r2, int n_ov, const double *__restric
       h *= 2.0;
     }
     if (!done) {
-      double lo, hi, flo;
-      if (a < b) { lo = a; hi = b; flo = fa; } else { lo = b; hi = a; flo = fb; }
+      double lo, hi, flo, fhi;
+      if (a < b) { lo = a; hi = b; flo = fa; fhi = fb; } else { lo = b; hi = a; flo = fb; fhi = fa; }
       double E, f, df;
       if (fabs(fa) <= fabs(fb)) { E = a; f = fa; df = da; } else { E = b; f = fb; df = db; }
+      int kept = 0;  // -1: the last update moved lo, +1: it moved hi
       nsteps = -1;
       for (int it = 1; it <= max_steps; ++it) {
         double En = df != 0.0 ? E - f / df : lo - 1.0;
-        if (!(lo < En && En < hi)) En = 0.5 * (lo + hi);
+        if (!(lo < En && En < hi)) {
+          // false position on the bracket, the Illinois way: the f of an end
+          // kept through two updates in a row is halved
+          En = (lo * fhi - hi * flo) / (fhi - flo);
+          if (!(lo < En && En < hi)) En = 0.5 * (lo + hi);
+        }
         if (fabs(En - E) < tol) {
           E = En;
           nsteps = it;
@@ -172,7 +178,17 @@ ev_solve_kernel(const double *__restrict__ r2, int n_ov, const double *__restric
           nsteps = it;
           break;
         }
-        if ((f > 0.0) == (flo > 0.0)) { lo = E; flo = f; } else { hi = E; }
+        if ((f > 0.0) == (flo > 0.0)) {
+          lo = E;
+          flo = f;
+          if (kept == -1) fhi *= 0.5;
+          kept = -1;
+        } else {
+          hi = E;
+          fhi = f;
+          if (kept == 1) flo *= 0.5;
+          kept = 1;
+        }
       }
       root = E;
     }
