@@ -150,7 +150,9 @@ def qp_root(fun, E0, eta, tol, max_steps):
     kept = 0                         # -1: the last update moved lo, +1: it moved hi
     for it in range(1, max_steps + 1):
         En = E - f / df if df != 0.0 else lo - 1.0
-        if not (lo < En < hi):
+        # a step onto an end is kept: at a root found at an end the step
+        # rounds to zero, and that is convergence, not a step out
+        if not (lo <= En <= hi):
             # false position on the bracket, the Illinois way: the f of an end
             # kept through two updates in a row is halved
             En = (lo * fhi - hi * flo) / (fhi - flo)

@@ -161,7 +161,9 @@ ev_solve_kernel(const double *__restrict__ r2, int n_ov, const double *__restric
       nsteps = -1;
       for (int it = 1; it <= max_steps; ++it) {
         double En = df != 0.0 ? E - f / df : lo - 1.0;
-        if (!(lo < En && En < hi)) {
+        // a step onto an end is kept: at a root found at an end the step
+        // rounds to zero, and that is convergence, not a step out
+        if (!(lo <= En && En <= hi)) {
           // false position on the bracket, the Illinois way: the f of an end
           // kept through two updates in a row is halved
           En = (lo * fhi - hi * flo) / (fhi - flo);
