@@ -37,6 +37,17 @@ def test_qp_root_finds_the_roots_of_known_equations():
         assert np.min(np.abs(roots - E)) < 1e-3   # one of the scanned roots
 
 
+def test_qp_root_accepts_a_root_found_at_a_bracket_end():
+    """f(E) = E - r + 1e-17: the representable root r evaluates to f = 1e-17 > 0,
+    so r becomes the bracket's upper end and the next Newton step rounds to
+    exactly r.  That is convergence (two steps), not a step out of the bracket
+    (which would bisect towards r for ~30 steps)."""
+    r = 0.3
+    E, it = EV.qp_root(lambda x: (x - r + 1e-17, 1.0), 0.31, 0.004, 1e-10, 200)
+    assert 0 < it <= 3
+    assert abs(E - r) < 1e-15
+
+
 def test_first_iteration_is_the_g0w0_quasiparticle_solution():
     """With e^(0) = eps the first iteration solves the G0W0 quasiparticle
     equation; for weak coupling the root is unique, so it equals the Newton
