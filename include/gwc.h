@@ -40,7 +40,7 @@ enum gwc_status {
   GWC_ERR_FACTORIZATION = -5,   /* exactly singular pivot in the LU of 1 - Pi(z) */
   GWC_ERR_OUT_OF_MEMORY = -6,
   GWC_ERR_DEVICE = -7,          /* any other HIP runtime failure */
-  GWC_ERR_UNSUPPORTED = -8      /* a valid request this build does not implement */
+  GWC_ERR_UNSUPPORTED = -8      /* a valid request the library does not implement */
 };
 
 enum gwc_mode {
