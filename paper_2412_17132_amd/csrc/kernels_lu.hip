@@ -111,8 +111,7 @@ struct PanelShared {
 template <int RPT, int W, int WPE>
 __global__ void __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(WPE)))
 lu_panel_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0,
-                int *__restrict__ piv_g, int *__restrict__ moves_g, double2 *__restrict__ linv_g,
-                int *__restrict__ status) {
+                int *__restrict__ piv_g, int *__restrict__ moves_g, int *__restrict__ status) {
   static_assert(2 * W <= WMAX, "a pair of column blocks wider than the shared buffers");
   __shared__ PanelShared sh;
   const int f = blockIdx.x;
@@ -449,7 +448,7 @@ lu_linv_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, int 
 // A[K0.., kpre..K0] A[kpre..K0, ..] when kpre >= 0 (a later panel of a
 // grouped step, whose rows the wide trailing update skips).
 __global__ void __launch_bounds__(256)
-lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0, int F,
+lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int K0, int F,
                    int nchunks, int c_start, int c_end, int kpre, int u12,
                    const int *__restrict__ moves_g, const double2 *__restrict__ linv_g) {
   __shared__ int mv[1 + 2 * MAX_MOVES];
@@ -458,7 +457,6 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
   if (!xcd_map(blockIdx.x, nchunks, F, f, chunk)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int n = N + R;
   const int kbo = min(NBO, N - K0);
   const int c0 = c_start + chunk * SW, cw = min(SW, c_end - c0);
   double2 *A = G + (long long)f * gs;
@@ -678,8 +676,8 @@ int lu_max_order() { return 24 * PT; }
 // workgroups per CU, where that costs at most a small spill)
 template <int RPT, int W, int WPE>
 static void launch_panel(int F, double2 *G, long long gs, int ldg, int N, int R, int K0, int *piv,
-                         int *moves, double2 *linv, int *status, hipStream_t stream) {
-  lu_panel_kernel<RPT, W, WPE><<<F, PT, 0, stream>>>(G, gs, ldg, N, R, K0, piv, moves, linv, status);
+                         int *moves, int *status, hipStream_t stream) {
+  lu_panel_kernel<RPT, W, WPE><<<F, PT, 0, stream>>>(G, gs, ldg, N, R, K0, piv, moves, status);
 }
 
 namespace {
@@ -696,21 +694,21 @@ struct LuLaunch {
     const int rpt = (N + R + PT - 1) / PT;
     // register block v[RPT][W] kept at <= 128 VGPRs; up to 512 rows take the
     // two-row form too (the one-row form spills its update accumulators)
-    if (rpt <= 2) launch_panel<2, 8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 3) launch_panel<3, 8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 4) launch_panel<4, 8, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 6) launch_panel<6, 4, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 8) launch_panel<8, 4, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 12) launch_panel<12, 2, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else if (rpt <= 16) launch_panel<16, 1, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
-    else launch_panel<24, 1, 1>(F, G, gs, ldg, N, R, K0, piv, moves, linv, status, s);
+    if (rpt <= 2) launch_panel<2, 8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, status, s);
+    else if (rpt <= 3) launch_panel<3, 8, 4>(F, G, gs, ldg, N, R, K0, piv, moves, status, s);
+    else if (rpt <= 4) launch_panel<4, 8, 1>(F, G, gs, ldg, N, R, K0, piv, moves, status, s);
+    else if (rpt <= 6) launch_panel<6, 4, 1>(F, G, gs, ldg, N, R, K0, piv, moves, status, s);
+    else if (rpt <= 8) launch_panel<8, 4, 1>(F, G, gs, ldg, N, R, K0, piv, moves, status, s);
+    else if (rpt <= 12) launch_panel<12, 2, 1>(F, G, gs, ldg, N, R, K0, piv, moves, status, s);
+    else if (rpt <= 16) launch_panel<16, 1, 1>(F, G, gs, ldg, N, R, K0, piv, moves, status, s);
+    else launch_panel<24, 1, 1>(F, G, gs, ldg, N, R, K0, piv, moves, status, s);
     lu_linv_kernel<<<F, 256, 0, s>>>(G, gs, ldg, N, K0, linv);
   }
   // row moves of the panel at K0 on columns [c0, c1); with u12 also its U rows
   void swap_u12(int K0, int c0, int c1, int kpre, int u12) const {
     const int nch = (c1 - c0 + SW - 1) / SW;
     if (nch < 1) return;
-    lu_swap_u12_kernel<<<NXCD * fgroups * nch, 256, 0, s>>>(G, gs, ldg, N, R, K0, F, nch, c0, c1, kpre,
+    lu_swap_u12_kernel<<<NXCD * fgroups * nch, 256, 0, s>>>(G, gs, ldg, N, K0, F, nch, c0, c1, kpre,
                                                              u12, moves, linv);
   }
   // rows [r0, n) x columns [c0, c1) -= A[.., K range] A[K range, ..]
