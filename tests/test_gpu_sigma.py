@@ -8,7 +8,7 @@ import pytest
 
 import paper_2412_17132_amd as gwc
 from oracle import sigma as OS
-from workloads import CONFIGS, EV_PER_HA, system_from_config
+from workloads import CONFIGS, system_from_config
 from workloads.configs import small_config
 
 pytestmark = pytest.mark.gpu

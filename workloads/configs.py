@@ -8,7 +8,7 @@ in eV here and converted to Hartree by the generator.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field, replace
+from dataclasses import dataclass, replace
 from typing import Optional, Tuple
 
 EV_PER_HA = 27.211386245988
