@@ -1,17 +1,20 @@
 #!/usr/bin/env python
 """Throughput benchmark of the GW+C core-level path on one MI355X.
 
-One step = one pass of the whole path over the benzene-sized workload
-(N_basis = 300, N_occ = 21 with 6 C1s levels, N_aux = 1200, 32 imaginary and
-400 real frequencies per core, eta = 0.1 eV): gwc_sigma_core in FULL mode for
-all 6 core states (Pi builds, LUs, quadrature, residues, E_QP) followed by
-gwc_spectral_cumulant for each core (n_t = 2^18, 0.01 eV).  Inputs are
-resident in HBM before the timed region.  The metric is core-state solves per
-second (one solve = Sigma^c_n on its grid + E_QP + A_n(w)).
+One step = one core-state solve of the benzene-sized workload (N_basis = 300,
+N_occ = 21 with 6 C1s levels, N_aux = 1200, 32 imaginary and 400 real
+frequencies per core, eta = 0.1 eV): gwc_sigma_core in FULL mode for one core
+state (Pi builds, LUs, quadrature, residues, E_QP) followed by
+gwc_spectral_cumulant (n_t = 2^18, 0.01 eV); consecutive steps take the cores
+in rotation.  Inputs are resident in HBM before the timed region.  The metric
+is core-state solves per second.
 
 Printed: one JSON line with the throughput, the Pi-build roofline (algorithmic
-FP64 flops / HIP-event kernel time against the 78.6 TFLOP/s FP64 MFMA peak)
-and the CPU oracle timed on a bounded sample of the same workload.
+FP64 flops / HIP-event kernel time against the 78.6 TFLOP/s FP64 MFMA peak),
+the CPU oracle timed on a bounded sample of the same workload (child process),
+and optional legs (precision forms, DECOUPLED mode, whole c3 / c4 core states,
+CD-WAC, the fully analytic route, evGW0, peak probes), each started only while
+its estimated duration fits the wall-clock limit.
 """
 from __future__ import annotations
 
@@ -22,6 +25,7 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -72,75 +76,116 @@ def _traffic_per_task():
     return t.get("bytes_per_task")
 
 
-def cpu_baseline(system, mode, n_tasks_per_core, budget_tasks=24):
-    """Times the oracle on a bounded sample and extrapolates to solves/s:
-    the imaginary axis of all cores, `budget_tasks` residue tasks, and one
-    cumulant at full size."""
-    import numpy as np
-
-    from oracle import cumulant as OC
-    from oracle import sigma as OS
-    from workloads import EV_PER_HA
-
-    threads = None
+def _blas_threads():
+    """Threads of the BLAS behind NumPy/SciPy (what the oracle's GEMMs and
+    factorisations use)."""
     try:
         from threadpoolctl import threadpool_info
         for info in threadpool_info():
             if info.get("internal_api") in ("openblas", "mkl", "blis"):
-                threads = int(info.get("num_threads"))
-                break
+                return int(info.get("num_threads"))
     except Exception:
         pass
-    if threads is None:
-        threads = os.cpu_count()
+    return os.cpu_count()
 
-    s = system
-    cores = [int(n) for n in s.core_idx]
+
+def cpu_baseline_child(args):
+    """The oracle timed on a bounded sample of one core-state solve (FULL mode,
+    core 0 of the workload), in a process of its own (no torch, no GPU).
+
+    Timed: the imaginary axis of the core in full (one Cholesky per node, all
+    N_basis border vectors), an evenly strided sample of its residue tasks
+    (one pivoted LU each) until --cpu-seconds is spent, the quadrature at every
+    point, and one full-size cumulant.  The solve time is extrapolated to all of
+    the core state's residue tasks by the mean task time.  Prints one JSON line."""
+    import numpy as np
+
+    from oracle import cumulant as OC
+    from oracle import sigma as OS
+    from workloads import CONFIGS, EV_PER_HA, system_from_config
+
+    s = system_from_config(CONFIGS[args.config])
+    c, n = 0, int(s.core_idx[0])
     L = OS.ov_matrix(s.M_ov)
     d = OS.transition_energies(s.eps, s.n_occ)
     t0 = time.perf_counter()
-    W = OS.w_imag_axis(L, d, s.M_oo, s.M_ov, cores, s.omega_imag)
+    W = OS.w_imag_axis(L, d, s.M_oo, s.M_ov, [n], s.omega_imag)[0]
     t_imag = time.perf_counter() - t0
 
-    rng = np.random.default_rng(0)
+    grid = [float(x) for x in s.omega_real[c]] + [float(s.eps[n])]
+    tasks = []
+    for j, w in enumerate(grid):
+        m_subset = None if args.mode == "full" or j == len(grid) - 1 else [n]
+        tasks += [(m, z) for m, _, z in OS.residue_terms(s.eps, s.occ, w, s.eta, m_subset)]
+    stride = max(1, len(tasks) // 997)
+    order = [k for r in range(stride) for k in range(r, len(tasks), stride)]
     done = 0
     t0 = time.perf_counter()
-    while done < budget_tasks:
-        c = int(rng.integers(len(cores)))
-        j = int(rng.integers(s.omega_real.shape[1]))
-        n = cores[c]
-        for m, f, z in OS.residue_terms(s.eps, s.occ, float(s.omega_real[c, j]), s.eta):
-            OS.screened_element(L, d, OS.pair_vector(s.M_oo, s.M_ov, n, m), z)
-            done += 1
-            if done >= budget_tasks:
-                break
+    for k in order:
+        m, z = tasks[k]
+        OS.screened_element(L, d, OS.pair_vector(s.M_oo, s.M_ov, n, m), z)
+        done += 1
+        if time.perf_counter() - t0 > args.cpu_seconds:
+            break
     t_task = (time.perf_counter() - t0) / done
 
-    c = 0
-    n = cores[c]
-    im = np.zeros(s.omega_real.shape[1])
     t0 = time.perf_counter()
-    I = OS.imag_integral(W[c], s.eps, s.omega_imag, s.w_imag, float(s.omega_real[c, 0]))
-    t_quad = (time.perf_counter() - t0) * (s.omega_real.shape[1] + 1)
-    im[: im.size // 2] = -1e-3
+    for w in grid:
+        OS.imag_integral(W, s.eps, s.omega_imag, s.w_imag, w)
+    t_quad = time.perf_counter() - t0
+
+    im = np.zeros(len(grid) - 1)
+    im[: im.size // 2] = -1e-3  # the cumulant's cost does not depend on the values
     e_qp = float(s.eps[n]) - 0.8
     t0 = time.perf_counter()
-    OC.spectral_cumulant(s.omega_real[c], im, float(s.eps[n]), e_qp, 0.1 / EV_PER_HA, 2 ** 18,
+    OC.spectral_cumulant(s.omega_real[c], im, float(s.eps[n]), e_qp, s.eta, 2 ** 18,
                          0.01 / EV_PER_HA, 3500, e_qp - 30 / EV_PER_HA)
     t_cum = time.perf_counter() - t0
-    del I
 
-    t_solve = t_imag / len(cores) + n_tasks_per_core * t_task + t_quad + t_cum
-    return {
+    t_solve = t_imag + len(tasks) * t_task + t_quad + t_cum
+    print(json.dumps({
         "value": 1.0 / t_solve,
         "unit": "solves/s",
-        "cores": threads,
+        "cores": _blas_threads(),
         "kind": "oracle",
-        "sample": (f"imaginary axis of all {len(cores)} cores ({t_imag:.1f} s), {done} residue "
-                   f"tasks ({t_task * 1e3:.0f} ms each), one 2^18-point cumulant ({t_cum:.1f} s); "
-                   f"extrapolated to {n_tasks_per_core:.0f} residue tasks per core-state solve"),
-    }
+        "sample": (f"one {args.mode.upper()} core-state solve of {args.config} (core 0): imaginary axis "
+                   f"in full ({t_imag:.1f} s), {done} of its {len(tasks)} residue tasks evenly "
+                   f"strided ({t_task * 1e3:.1f} ms each), quadrature at all {len(grid)} points "
+                   f"({t_quad:.2f} s), one 2^18-point cumulant ({t_cum:.1f} s); extrapolated by "
+                   f"task count to {t_solve:.0f} s per solve"),
+        "sampled_s": t_imag + done * t_task + t_quad + t_cum,
+        "cpu_model": _cpu_model(),
+    }), flush=True)
 
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(args, timeout_s=150):
+    """Runs cpu_baseline_child in a child process with a time limit and returns
+    its record (or the reason it has none)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--config", args.config,
+           "--mode", args.mode, "--cpu-seconds", str(args.cpu_seconds)]
+    try:
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        return {"value": None, "unit": "solves/s", "kind": "oracle", "error": f"timed out after {timeout_s} s"}
+    for line in reversed(r.stdout.strip().splitlines()):
+        try:
+            return json.loads(line)
+        except ValueError:
+            continue
+    return {"value": None, "unit": "solves/s", "kind": "oracle",
+            "error": f"exit {r.returncode}: {r.stderr.strip()[-300:]}"}
 
 def residue_task_count(eps, occ, core_idx, omega_real, mode="full"):
     """Residue terms (n, w, m) with a nonzero prefactor (Eq. cd_prefactors:
@@ -389,34 +434,101 @@ def serve_main(args):
     emit(line, args.jsonl)
 
 
+class Guard:
+    """Wall-clock guard of the optional legs: a leg starts only when its
+    estimated duration still fits before the limit (seconds since the process
+    started); a leg that does not start is recorded as skipped."""
+
+    def __init__(self, limit_s):
+        self.limit = float(limit_s)
+
+    def elapsed(self):
+        return time.perf_counter() - T_START
+
+    def run(self, res, name, estimate_s, fn):
+        if self.elapsed() + estimate_s > self.limit:
+            res[name] = {"skipped": "budget", "estimate_s": round(estimate_s, 1),
+                         "elapsed_s": round(self.elapsed(), 1), "limit_s": self.limit}
+            print(f"bench: leg {name} skipped (estimate {estimate_s:.0f} s, elapsed "
+                  f"{self.elapsed():.0f} s of {self.limit:.0f} s)", file=sys.stderr, flush=True)
+            return
+        print(f"bench: leg {name} (estimate {estimate_s:.0f} s, elapsed {self.elapsed():.0f} s)",
+              file=sys.stderr, flush=True)
+        t = time.perf_counter()
+        res[name] = fn()
+        res[name]["leg_wall_s"] = round(time.perf_counter() - t, 2)
+
+
+def _rate(t):
+    return t["flops"] / (t["total_ms"] / 1e3) / 1e12 if t["total_ms"] > 0 else 0.0
+
+
+def _sigma_rel(ref_out, out):
+    """max and median over points of |dSigma^c| / max|Sigma^c_ref| (one core)."""
+    import numpy as np
+    a = ref_out["sigma_c"][0].cpu().numpy()
+    b = out["sigma_c"][0].cpu().numpy()
+    ca = a[..., 0] + 1j * a[..., 1]
+    cb = b[..., 0] + 1j * b[..., 1]
+    rel = np.abs(cb - ca) / np.max(np.abs(ca))
+    return rel
+
+
+def _compare_solves(ref, res, eta, n_out, d_omega):
+    """E_QP, satellite-position and Sigma^c deviations of one set of core-state
+    solves from another (both {core: (out, A, z)})."""
+    import numpy as np
+    from workloads import EV_PER_HA
+    deq, worst, rels = [], 0.0, []
+    for c, (out, A, z) in res.items():
+        if c not in ref:
+            continue
+        r_out, r_A, r_z = ref[c]
+        eq_r, eq_m = float(r_out["e_qp"][0]), float(out["e_qp"][0])
+        deq.append(abs(eq_m - eq_r))
+        wr = eq_r - 30 / EV_PER_HA + np.arange(n_out) * d_omega
+        wm = eq_m - 30 / EV_PER_HA + np.arange(n_out) * d_omega
+        pr = _satellites(wr, r_A.cpu().numpy(), eq_r, float(r_z[0]), eta)
+        pm = _satellites(wm, A.cpu().numpy(), eq_m, float(z[0]), eta)
+        for p in pr:
+            if pm:
+                worst = max(worst, float(np.min(np.abs(np.asarray(pm) - p))))
+        if out.get("sigma_c") is not None and r_out.get("sigma_c") is not None:
+            rels.append(_sigma_rel(r_out, out))
+    rec = {"cores_compared": len(deq),
+           "e_qp_max_dev_mev": float(max(deq) * EV_PER_HA * 1e3) if deq else None,
+           "satellite_max_shift_mev": worst * EV_PER_HA * 1e3}
+    if rels:
+        allr = np.concatenate(rels)
+        rec["sigma_c_rel_dev"] = {"max": float(allr.max()), "median": float(np.median(allr))}
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6, help="timed core-state solves")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed core-state solves before them")
     ap.add_argument("--config", default="c2", help="workload (default: the benzene-sized c2)")
     ap.add_argument("--mode", default="full", choices=["full", "decoupled"])
     ap.add_argument("--n-real", type=int, default=None,
                     help="override the real grid size (a reduced run, not the named workload)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "bf16x3", "fp16x3", "fp8"],
                     help="precision of the timed path (default FP64)")
-    ap.add_argument("--compare", default="bf16x3", choices=["none", "bf16x3", "fp16x3", "fp8"],
-                    help="also time this mixed-precision form and report its speed-up and its "
-                         "E_QP / satellite-position errors against the FP64 path")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-peaks", action="store_true", help="skip the peak-rate probes")
-    ap.add_argument("--no-wac", action="store_true",
-                    help="skip the CD-WAC leg (the paper's settings) reported beside the CD value")
-    ap.add_argument("--no-decoupled", action="store_true",
-                    help="skip the DECOUPLED-mode leg reported beside the FULL value")
-    ap.add_argument("--no-analytic", action="store_true",
-                    help="skip the fully analytic G0W0 leg (Casida eigensolve + pole sums)")
-    ap.add_argument("--no-evgw", action="store_true",
-                    help="skip the evGW0 leg (all states' energies iterated; M_vv of the workload)")
+    ap.add_argument("--compare", default="bf16x3,fp8",
+                    help="comma-separated mixed-precision forms also timed (one solve per core "
+                         "state) with their E_QP / satellite / Sigma^c deviations from FP64, or none")
+    ap.add_argument("--legs", default="cpu,mixed,decoupled,c3,c4,wac,analytic,evgw0,peaks",
+                    help="optional legs after the timed region, in order (comma-separated)")
+    ap.add_argument("--time-limit", type=float, default=450.0,
+                    help="start no optional leg that would end later than this many seconds "
+                         "after the process started")
     ap.add_argument("--sample-points", type=int, default=0,
                     help="sampled run for large workloads (c3, c4): one core state at 1 and this "
                          "many real points, extrapolated to the full grid")
-    ap.add_argument("--cpu-tasks", type=int, default=24)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="residue-task time budget of the CPU oracle sample")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark instead: a Poisson stream of single-core-state "
                          "requests through the continuous-batching server")
@@ -433,6 +545,8 @@ def main():
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
 
+    if args.cpu_baseline_child:
+        return cpu_baseline_child(args)
     if args.calibrate_copy:
         import torch
         a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
@@ -443,7 +557,6 @@ def main():
         print(json.dumps({"calibration": "copy", "bytes_read": 2 ** 30, "bytes_written": 2 ** 30,
                           "launches": 3}))
         return
-
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout "
               "is a design note, not an implemented path.", file=sys.stderr)
@@ -460,262 +573,291 @@ def main():
     from workloads import CONFIGS, EV_PER_HA, system_from_config
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.steps < 1 or args.warmup < 0:
+        raise SystemExit("--steps must be >= 1 and --warmup >= 0")
     dev = torch.device("cuda:0")
+    guard = Guard(args.time_limit)
     cfg = CONFIGS[args.config]
     over = {} if args.n_real is None else {"n_real": args.n_real}
     s = system_from_config(cfg, **over)
     d = gwc.to_device(s, dev)
     n_core = s.n_core
-    n_t, d_omega = 2 ** 18, 0.01 / EV_PER_HA
-    n_out = 3500
+    n_t, d_omega, n_out = 2 ** 18, 0.01 / EV_PER_HA, 3500
 
-    def step(precision=args.precision, wac=None):
-        out = gwc.gwc_sigma_core(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],
-                                 d["omega_imag"], d["w_imag"], d["omega_real"], d["eta"],
-                                 mode=args.mode, precision=precision, wac=wac)
-        e_qp = out["e_qp"].cpu().numpy()
-        spectra = []
-        for c in range(n_core):
-            n = int(s.core_idx[c])
-            A, z = gwc.gwc_spectral_cumulant(d["omega_real"][c], out["im_sigma_dec"][c],
-                                             float(s.eps[n]), float(e_qp[c]), s.eta, n_t, d_omega,
-                                             n_out, float(e_qp[c]) - 30 / EV_PER_HA)
-            spectra.append((A, z))
-        return out, spectra
+    def solve(c, precision=args.precision, mode=args.mode, wac=None, sh=s, sd=d):
+        """One core-state solve: Sigma^c_n on its grid (FULL) or Sigma^c_n(eps_n)
+        plus Im Sigma^dec (DECOUPLED), E_QP, and A_n(w) from the cumulant."""
+        out = gwc.gwc_sigma_core(sd["eps"], sd["occ"], sd["M_oo"], sd["M_ov"], sd["core_idx"][c:c + 1],
+                                 sd["omega_imag"], sd["w_imag"], sd["omega_real"][c:c + 1], sd["eta"],
+                                 mode=mode, precision=precision, wac=wac)
+        e_qp = float(out["e_qp"][0])
+        n = int(sh.core_idx[c])
+        A, z = gwc.gwc_spectral_cumulant(sd["omega_real"][c], out["im_sigma_dec"][0], float(sh.eps[n]),
+                                         e_qp, sh.eta, n_t, d_omega, n_out, e_qp - 30 / EV_PER_HA)
+        return out, A, z
 
-    for _ in range(args.warmup):
-        step()
+    tasks_of = [residue_task_count(s.eps, s.occ, s.core_idx[c:c + 1], s.omega_real[c:c + 1], args.mode)
+                for c in range(n_core)]
+    print(f"bench: {cfg.name} {args.mode} {args.precision}, {args.warmup} warm-up + {args.steps} timed "
+          f"core-state solves", file=sys.stderr, flush=True)
+    for k in range(args.warmup):
+        solve(k % n_core)
     torch.cuda.synchronize()
     gwc.timing_enable(True)
-    lat = []
+    lat, last = [], {}
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         ts = time.perf_counter()
-        last = step()
+        last[k % n_core] = solve(k % n_core)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    pi = gwc.timing_get("pi_build_f64" if args.precision == "fp64" else "pi_build_mixed")
+    pi_name = "pi_build_f64" if args.precision == "fp64" else "pi_build_mixed"
+    pi = gwc.timing_get(pi_name)
     lu = gwc.timing_get("lu_bordered")
     gwc.timing_enable(False)
+    t_step = elapsed / args.steps
+    print(f"bench: timed region {elapsed:.2f} s ({t_step:.3f} s per core-state solve)",
+          file=sys.stderr, flush=True)
 
-    solves = args.steps * n_core
-    value = solves / elapsed
-    n_tasks = residue_task_count(s.eps, s.occ, s.core_idx, s.omega_real, args.mode)
+    n_tasks = sum(tasks_of[k % n_core] for k in range(args.steps))
     launches = max(pi["launches"], 1)
-    achieved = pi["flops"] / (pi["total_ms"] / 1e3) / 1e12 if pi["total_ms"] > 0 else 0.0
+    achieved = _rate(pi)
     tpt = _traffic_per_task()
-    pi_tasks = args.steps * (len(s.omega_imag) * n_core + n_tasks)
+    pi_tasks = args.steps * len(s.omega_imag) + n_tasks
     tpl = None if tpt is None else tpt * pi_tasks / launches
     peak = FP64_MFMA_PEAK_TFLOPS
     if args.precision != "fp64":
-        # three 16-bit MFMA products per algorithmic multiply-add; dense 16-bit peak
+        # three 16-bit (or 8-bit) MFMA products per algorithmic multiply-add
         achieved, peak, tpl = 3.0 * achieved, MIXED_MFMA_PEAK_TFLOPS[args.precision], None
-    roofline = {
-        "bound": "mfma",
-        "achieved": achieved,
-        "peak": peak,
-        "unit": "TFLOP/s",
-        "frac": achieved / peak,
-        "traffic": tpl,
-        "kernel": "pi_build_f64",
-        "avg_launch_ms": pi["total_ms"] / launches,
-        "flops_per_launch": pi["flops"] / launches,
-    }
-    lu_achieved = lu["flops"] / (lu["total_ms"] / 1e3) / 1e12 if lu["total_ms"] > 0 else 0.0
     res = {
         "metric": METRIC,
-        "value": value,
+        "value": args.steps / elapsed,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": t_step * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else args.precision,
         "data": "synthetic",
         "config": {
-            "workload": f"{cfg.name}: {cfg.description}" + ("" if args.n_real is None else f" (n_real={args.n_real})"),
+            "workload": (f"{cfg.name}: {cfg.description}; one step = one core-state solve "
+                         f"({args.mode.upper()} Sigma^c on {s.omega_real.shape[1]} points + E_QP + "
+                         f"A(w)), cores in rotation" + ("" if args.n_real is None else
+                                                        f" (n_real={args.n_real})")),
             "n_basis": cfg.n_basis, "n_occ": cfg.n_occ, "n_core": n_core, "n_aux": cfg.n_aux,
             "n_imag": cfg.n_imag, "n_real": s.omega_real.shape[1], "eta_ev": cfg.eta_ev,
-            "mode": args.mode, "precision": args.precision, "residue_tasks_per_step": n_tasks,
-            "cumulant_n_t": n_t, "parallelism": "single-gpu",
+            "mode": args.mode, "precision": args.precision,
+            "residue_tasks_timed": n_tasks, "cumulant_n_t": n_t, "parallelism": "single-gpu",
         },
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                      "per": "step (all core states)"},
-        "roofline": roofline,
+                      "per": "core-state solve"},
+        "roofline": {
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": tpl,
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": pi_name,
+            "launches": pi["launches"],
+            "avg_launch_ms": pi["total_ms"] / launches,
+            "flops_per_launch": pi["flops"] / launches,
+        },
         "kernels": {
-            "pi_build_f64": {"ms": pi["total_ms"], "launches": pi["launches"], "tflops": achieved},
-            "lu_bordered": {"ms": lu["total_ms"], "launches": lu["launches"], "tflops": lu_achieved},
+            pi_name: {"ms": pi["total_ms"], "launches": pi["launches"], "tflops": _rate(pi)},
+            "lu_bordered": {"ms": lu["total_ms"], "launches": lu["launches"], "tflops": _rate(lu)},
         },
     }
-    if args.compare != "none" and args.precision == "fp64":
-        step(args.compare)  # warm-up of the mixed form
-        torch.cuda.synchronize()
-        gwc.timing_enable(True)
-        tm = time.perf_counter()
-        for _ in range(args.steps):
-            mixed = step(args.compare)
-        torch.cuda.synchronize()
-        el_m = time.perf_counter() - tm
-        pim = gwc.timing_get("pi_build_mixed")
-        gwc.timing_enable(False)
-        ref_out, ref_spec = last
-        mx_out, mx_spec = mixed
-        deq = np.abs(mx_out["e_qp"].cpu().numpy() - ref_out["e_qp"].cpu().numpy())
-        w_axis = None
-        worst = 0.0
-        for c in range(n_core):
-            eq_r = float(ref_out["e_qp"][c]); eq_m = float(mx_out["e_qp"][c])
-            wr = eq_r - 30 / EV_PER_HA + np.arange(n_out) * d_omega
-            wm = eq_m - 30 / EV_PER_HA + np.arange(n_out) * d_omega
-            pr = _satellites(wr, ref_spec[c][0].cpu().numpy(), eq_r, float(ref_spec[c][1][0]), s.eta)
-            pm = _satellites(wm, mx_spec[c][0].cpu().numpy(), eq_m, float(mx_spec[c][1][0]), s.eta)
-            for p in pr:
-                if pm:
-                    worst = max(worst, float(np.min(np.abs(np.asarray(pm) - p))))
-        sc_err = None
-        if args.mode == "full":
-            a = ref_out["sigma_c"].cpu().numpy(); b = mx_out["sigma_c"].cpu().numpy()
-            rel = np.abs((b - a)[..., 0] + 1j * (b - a)[..., 1]) / np.max(np.abs(a[..., 0] + 1j * a[..., 1]))
-            sc_err = {"max": float(rel.max()), "median": float(np.median(rel))}
-        pim_tf = pim["flops"] / (pim["total_ms"] / 1e3) / 1e12 if pim["total_ms"] > 0 else 0.0
-        res["mixed"] = {
-            "precision": args.compare,
-            "value": solves / el_m,
-            "ms_per_step": el_m / args.steps * 1e3,
-            "speedup_vs_fp64": elapsed / el_m,
-            "pi_build_ms": pim["total_ms"],
-            "pi_build_algorithmic_tflops": pim_tf,
-            "pi_build_mfma_tflops": 3.0 * pim_tf,
-            "pi_build_mfma_peak_tflops": MIXED_MFMA_PEAK_TFLOPS[args.compare],
-            "pi_build_mfma_frac": 3.0 * pim_tf / MIXED_MFMA_PEAK_TFLOPS[args.compare],
-            "e_qp_max_err_mev": float(deq.max() * EV_PER_HA * 1e3),
-            "satellite_max_shift_mev": worst * EV_PER_HA * 1e3,
-            "sigma_c_rel_err": sc_err,
-        }
-    if not args.no_wac:
-        wp = gwc.wac_paper_settings()
-        step(args.precision, wp)  # warm-up
-        torch.cuda.synchronize()
-        tw = time.perf_counter()
-        for _ in range(args.steps):
-            wres = step(args.precision, wp)
-        torch.cuda.synchronize()
-        el_w = time.perf_counter() - tw
-        ref_out, ref_spec = last
-        w_out, w_spec = wres
-        deq = np.abs(w_out["e_qp"].cpu().numpy() - ref_out["e_qp"].cpu().numpy())
-        worst = 0.0
-        for c in range(n_core):
-            eq_r = float(ref_out["e_qp"][c]); eq_w = float(w_out["e_qp"][c])
-            wr = eq_r - 30 / EV_PER_HA + np.arange(n_out) * d_omega
-            ww = eq_w - 30 / EV_PER_HA + np.arange(n_out) * d_omega
-            pr = _satellites(wr, ref_spec[c][0].cpu().numpy(), eq_r, float(ref_spec[c][1][0]), s.eta)
-            pw = _satellites(ww, w_spec[c][0].cpu().numpy(), eq_w, float(w_spec[c][1][0]), s.eta)
-            for q in pr:
-                if pw:
-                    worst = max(worst, float(np.min(np.abs(np.asarray(pw) - q))))
-        sc_err = None
-        if args.mode == "full":
-            a = ref_out["sigma_c"].cpu().numpy(); b = w_out["sigma_c"].cpu().numpy()
-            rel = np.abs((b - a)[..., 0] + 1j * (b - a)[..., 1]) / np.max(np.abs(a[..., 0] + 1j * a[..., 1]))
-            sc_err = {"max": float(rel.max()), "median": float(np.median(rel))}
-        res["wac"] = {
-            "value": solves / el_w, "unit": "solves/s", "ms_per_step": el_w / args.steps * 1e3,
-            "speedup_vs_cd": elapsed / el_w,
-            "settings": {k: (v * EV_PER_HA if k in ("core_min", "core_max") else v) for k, v in wp.items()},
-            "settings_units": "core window in eV",
-            "reference_factorisations_per_step": n_core * (wp["n_core_pts"] + wp["n_val_pts"]),
-            "e_qp_max_dev_from_cd_mev": float(deq.max() * EV_PER_HA * 1e3),
-            "satellite_max_shift_from_cd_mev": worst * EV_PER_HA * 1e3,
-            "sigma_c_rel_dev_from_cd": sc_err,
-        }
-    if args.mode == "full" and not args.no_decoupled:
-        mode_full = args.mode
-        args.mode = "decoupled"
-        step()  # warm-up
+
+    legs = [x.strip() for x in args.legs.split(",") if x.strip()]
+    compare = [] if args.compare == "none" else [x.strip() for x in args.compare.split(",") if x.strip()]
+
+    def leg_cpu():
+        return cpu_baseline(args)
+
+    def leg_mixed(prec):
+        def run():
+            solve(0, prec)  # warm-up (also builds the split operands)
+            torch.cuda.synchronize()
+            gwc.timing_enable(True)
+            got = {}
+            tm = time.perf_counter()
+            for c in range(n_core):
+                got[c] = solve(c, prec)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - tm
+            pim = gwc.timing_get("pi_build_mixed")
+            lum = gwc.timing_get("lu_bordered")
+            gwc.timing_enable(False)
+            alg = _rate(pim)
+            rec = {"precision": prec, "value": n_core / el, "unit": "solves/s",
+                   "ms_per_step": el / n_core * 1e3, "speedup_vs_fp64": t_step / (el / n_core),
+                   "pi_build_ms": pim["total_ms"], "pi_build_algorithmic_tflops": alg,
+                   "pi_build_mfma_tflops": 3.0 * alg,
+                   "pi_build_mfma_peak_tflops": MIXED_MFMA_PEAK_TFLOPS[prec],
+                   "pi_build_mfma_frac": 3.0 * alg / MIXED_MFMA_PEAK_TFLOPS[prec],
+                   "lu_ms": lum["total_ms"]}
+            rec["vs_fp64"] = _compare_solves(last, got, s.eta, n_out, d_omega)
+            return rec
+        return run
+
+    def leg_decoupled():
+        solve(0, mode="decoupled")
         torch.cuda.synchronize()
         td = time.perf_counter()
-        for _ in range(args.steps):
-            step()
+        for c in range(n_core):
+            solve(c, mode="decoupled")
         torch.cuda.synchronize()
-        el_d = time.perf_counter() - td
-        args.mode = mode_full
-        res["decoupled"] = {
-            "value": solves / el_d, "unit": "solves/s", "ms_per_step": el_d / args.steps * 1e3,
-            "residue_tasks_per_step": residue_task_count(s.eps, s.occ, s.core_idx, s.omega_real,
-                                                             "decoupled"),
-            "precision": args.precision,
-        }
-    if args.mode == "full" and not args.no_analytic:
+        el = time.perf_counter() - td
+        return {"value": n_core / el, "unit": "solves/s", "ms_per_step": el / n_core * 1e3,
+                "residue_tasks": residue_task_count(s.eps, s.occ, s.core_idx, s.omega_real, "decoupled"),
+                "precision": args.precision}
+
+    def leg_wac():
+        wp = gwc.wac_paper_settings()
+        solve(0, wac=wp)
+        torch.cuda.synchronize()
+        got = {}
+        tw = time.perf_counter()
+        for c in range(n_core):
+            got[c] = solve(c, wac=wp)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - tw
+        rec = {"value": n_core / el, "unit": "solves/s", "ms_per_step": el / n_core * 1e3,
+               "speedup_vs_cd": t_step / (el / n_core),
+               "settings": {k: (v * EV_PER_HA if k in ("core_min", "core_max") else v) for k, v in wp.items()},
+               "settings_units": "core window in eV",
+               "reference_factorisations_per_solve": wp["n_core_pts"] + wp["n_val_pts"]}
+        rec["dev_from_cd"] = _compare_solves(last, got, s.eta, n_out, d_omega)
+        return rec
+
+    def leg_analytic():
         def astep():
             return gwc.gwc_sigma_analytic(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],
                                           d["omega_real"], d["eta"])
-        astep()  # warm-up
+        astep()
         torch.cuda.synchronize()
         gwc.timing_enable(True)
         ta = time.perf_counter()
-        for _ in range(args.steps):
-            aout = astep()
+        aout = astep()
         torch.cuda.synchronize()
-        el_a = time.perf_counter() - ta
+        el = time.perf_counter() - ta
         ja, jp = gwc.timing_get("jacobi_apply"), gwc.timing_get("jacobi_pairs")
         gwc.timing_enable(False)
-        ja_tf = ja["flops"] / (ja["total_ms"] / 1e3) / 1e12 if ja["total_ms"] > 0 else 0.0
-        ref_out = last[0]
-        deq = np.abs(aout["e_qp"].cpu().numpy() - ref_out["e_qp"].cpu().numpy())
-        res["analytic"] = {
-            "value": solves / el_a, "unit": "solves/s", "ms_per_step": el_a / args.steps * 1e3,
-            "speedup_vs_cd": elapsed / el_a,
-            "n_ov": int(s.M_ov.shape[1] * s.M_ov.shape[2]),
-            "jacobi_sweeps": int(aout["sweeps"][0]),
-            "jacobi_apply": {"ms_per_step": ja["total_ms"] / args.steps,
-                             "launches_per_step": ja["launches"] / args.steps,
-                             "avg_launch_ms": ja["total_ms"] / max(ja["launches"], 1),
-                             "bound": "alu", "achieved": ja_tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                             "unit": "TFLOP/s", "frac": ja_tf / FP64_VECTOR_PEAK_TFLOPS},
-            "jacobi_pairs_ms_per_step": jp["total_ms"] / args.steps,
-            "e_qp_dev_from_cd_mev": float(deq.max() * EV_PER_HA * 1e3),
-        }
-    if args.mode == "full" and not args.no_evgw:
+        ja_tf = _rate(ja)
+        deq = [abs(float(aout["e_qp"][c]) - float(last[c][0]["e_qp"][0])) for c in last]
+        return {"value": n_core / el, "unit": "solves/s (all core states in one call)",
+                "ms_per_call": el * 1e3, "n_ov": int(s.M_ov.shape[1] * s.M_ov.shape[2]),
+                "jacobi_sweeps": int(aout["sweeps"][0]),
+                "jacobi_apply": {"ms": ja["total_ms"], "launches": ja["launches"],
+                                 "avg_launch_ms": ja["total_ms"] / max(ja["launches"], 1),
+                                 "bound": "mfma", "achieved": ja_tf, "peak": FP64_MFMA_PEAK_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": ja_tf / FP64_MFMA_PEAK_TFLOPS},
+                "jacobi_pairs_ms": jp["total_ms"],
+                "e_qp_dev_from_cd_mev": float(max(deq) * EV_PER_HA * 1e3) if deq else None}
+
+    def leg_evgw0():
         from workloads import vv_block
         dvv = torch.as_tensor(vv_block(s), device=dev)
 
         def evstep():
             return gwc.gwc_evgw0(d["eps"], d["occ"], d["M_oo"], d["M_ov"], dvv, d["core_idx"],
                                  d["omega_real"], d["eta"])
-        evstep()  # warm-up
+        evstep()
         torch.cuda.synchronize()
         te = time.perf_counter()
-        for _ in range(args.steps):
-            eout = evstep()
+        eout = evstep()
         torch.cuda.synchronize()
-        el_e = time.perf_counter() - te
+        el = time.perf_counter() - te
         eq = eout["e_qp"].cpu().numpy()
         e1 = eout["e_first"].cpu().numpy()
         core = s.core_idx
-        res["evgw0"] = {
-            "value": solves / el_e, "unit": "solves/s (core states, every state iterated)",
-            "ms_per_step": el_e / args.steps * 1e3,
-            "states_iterated": int(s.n_basis), "outer_iterations": int(eout["outer"][0]),
-            "max_newton_steps": int(eout["newton"].max()),
-            "core_shift_g0w0_ev": [float(x) for x in (e1[core] - s.eps[core]) * EV_PER_HA],
-            "core_shift_evgw0_ev": [float(x) for x in (eq[core] - s.eps[core]) * EV_PER_HA],
-        }
-    if not args.no_peaks:
-        pk = measure_peaks(gwc)
-        res["peaks_measured"] = pk
-        if args.precision == "fp64":
-            res["roofline"]["peak_measured"] = pk["fp64_mfma_tflops"]
-            res["roofline"]["frac_of_measured"] = achieved / pk["fp64_mfma_tflops"]
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(s, args.mode, n_tasks / n_core, args.cpu_tasks)
-    emit(res, args.jsonl)
+        return {"value": n_core / el, "unit": "solves/s (core states; every state iterated)",
+                "ms_per_call": el * 1e3, "states_iterated": int(s.n_basis),
+                "outer_iterations": int(eout["outer"][0]), "max_newton_steps": int(eout["newton"].max()),
+                "core_shift_g0w0_ev": [float(x) for x in (e1[core] - s.eps[core]) * EV_PER_HA],
+                "core_shift_evgw0_ev": [float(x) for x in (eq[core] - s.eps[core]) * EV_PER_HA]}
 
+    def leg_whole(name, mode):
+        """One whole core state (core 0) of a larger workload, unsampled."""
+        def run():
+            cf = CONFIGS[name]
+            tg = time.perf_counter()
+            sh = system_from_config(cf)
+            sd = gwc.to_device(sh, dev)
+            t_gen = time.perf_counter() - tg
+            tasks = residue_task_count(sh.eps, sh.occ, sh.core_idx[:1], sh.omega_real[:1], mode)
+            torch.cuda.synchronize()
+            gwc.timing_enable(True)
+            tw = time.perf_counter()
+            out, A, z = solve(0, "fp64", mode, None, sh, sd)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - tw
+            p, u = gwc.timing_get("pi_build_f64"), gwc.timing_get("lu_bordered")
+            gwc.timing_enable(False)
+            e_qp = float(out["e_qp"][0])
+            del sd, out, A, z
+            torch.cuda.empty_cache()
+            return {"workload": f"{cf.name}: {cf.description}; core 0, {mode.upper()}, FP64, whole and "
+                                f"unsampled (no warm-up: first call on this system)",
+                    "value": 1.0 / el, "unit": "solves/s", "s_per_solve": el,
+                    "residue_tasks": tasks, "n_imag": cf.n_imag, "n_real": cf.n_real,
+                    "pi_build": {"ms": p["total_ms"], "launches": p["launches"], "tflops": _rate(p),
+                                 "frac": _rate(p) / FP64_MFMA_PEAK_TFLOPS},
+                    "lu_bordered": {"ms": u["total_ms"], "launches": u["launches"], "tflops": _rate(u)},
+                    "e_qp_shift_ev": (e_qp - float(sh.eps[0])) * EV_PER_HA,
+                    "setup_s": t_gen}
+        return run
+
+    def leg_peaks():
+        return measure_peaks(gwc)
+
+    # per-task time of the timed path, scaled by the Pi-build work of a task
+    # (N_aux^2 N_ov), estimates the larger workloads for the wall-clock guard
+    t_task = elapsed / max(n_tasks + args.steps * len(s.omega_imag), 1)
+
+    def scaled(name, mode):
+        cf = CONFIGS[name]
+        probe = system_from_config(cf, n_aux=1)  # energies and grids do not depend on N_aux
+        k = residue_task_count(probe.eps, probe.occ, probe.core_idx[:1], probe.omega_real[:1], mode)
+        w = (cf.n_aux / cfg.n_aux) ** 2 * (cf.n_ov / cfg.n_ov)
+        return 1.25 * (k + cf.n_imag) * t_task * w + 20.0
+
+    for leg in legs:
+        if leg == "cpu":
+            print("bench: cpu baseline (child process)", file=sys.stderr, flush=True)
+            res["cpu_baseline"] = leg_cpu()
+        elif leg == "mixed" and args.precision == "fp64":
+            for prec in compare:
+                guard.run(res.setdefault("mixed", {}), prec, 1.0 * (n_core + 1) * t_step + 5,
+                          leg_mixed(prec))
+        elif leg == "decoupled" and args.mode == "full":
+            guard.run(res, "decoupled", 0.3 * (n_core + 1) * t_step + 5, leg_decoupled)
+        elif leg == "c3" and args.config == "c2":
+            guard.run(res, "c3_full_fp64", scaled("c3", "full"), leg_whole("c3", "full"))
+        elif leg == "c4" and args.config == "c2":
+            guard.run(res, "c4_decoupled_fp64", scaled("c4", "decoupled"), leg_whole("c4", "decoupled"))
+        elif leg == "wac":
+            guard.run(res, "wac", 0.3 * (n_core + 1) * t_step + 5, leg_wac)
+        elif leg == "analytic" and args.mode == "full":
+            guard.run(res, "analytic", 10.0, leg_analytic)
+        elif leg == "evgw0" and args.mode == "full":
+            guard.run(res, "evgw0", 15.0, leg_evgw0)
+        elif leg == "peaks":
+            guard.run(res, "peaks_measured", 15.0, leg_peaks)
+            pk = res["peaks_measured"]
+            if "fp64_mfma_tflops" in pk and args.precision == "fp64":
+                res["roofline"]["peak_measured"] = pk["fp64_mfma_tflops"]
+                res["roofline"]["frac_of_measured"] = achieved / pk["fp64_mfma_tflops"]
+    res["wall_s"] = round(guard.elapsed(), 1)
+    emit(res, args.jsonl)
 
 if __name__ == "__main__":
     main()

@@ -420,7 +420,9 @@ typedef struct {
 } gwc_server_stats_t;
 int gwc_server_create(const gwc_server_config *cfg, gwc_server_handle *server);
 int gwc_server_submit(gwc_server_handle server, const gwc_request *request, int64_t *ticket);
-/* Blocks until the request has finished; fills `result` and returns its status. */
+/* Blocks until the request has finished; fills `result` and returns its status.
+ * A ticket is consumed by its wait: waiting on it again, or from a second
+ * thread while the first still waits, returns GWC_ERR_INVALID_ARG. */
 int gwc_server_wait(gwc_server_handle server, int64_t ticket, gwc_request_result *result);
 int gwc_server_stats(gwc_server_handle server, gwc_server_stats_t *stats);
 /* Finishes every queued request, then stops the workers. */

@@ -44,6 +44,7 @@ struct Request {
   size_t footprint = 0;
   // results
   bool done = false;
+  bool claimed = false;  // a gwc_server_wait holds this ticket (set under the server lock)
   int status = GWC_OK;
   std::string error;
   double e_qp = 0.0, sigma_x = 0.0, sigma_c_eps[2] = {0.0, 0.0}, z[2] = {0.0, 0.0};
@@ -250,9 +251,16 @@ int gwc_server_wait(gwc_server_handle srv, int64_t ticket, gwc_request_result *r
       auto it = srv->reqs.find(ticket);
       if (it == srv->reqs.end()) gwc::fail(GWC_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
       Request *rp = it->second.get();
+      // one waiter per ticket: a second wait would find the entry erased and
+      // its Request freed once the first returns
+      if (rp->claimed) gwc::fail(GWC_ERR_INVALID_ARG, "ticket %lld is already being waited on", (long long)ticket);
+      rp->claimed = true;
       srv->cv.wait(lock, [&] { return rp->done; });
-      r = std::move(it->second);
-      srv->reqs.erase(it);
+      // the map's iterator may be stale after the wait (other tickets were
+      // inserted or erased meanwhile): look the ticket up again
+      auto again = srv->reqs.find(ticket);
+      r = std::move(again->second);
+      srv->reqs.erase(again);
     }
     res->status = r->status;
     res->e_qp = r->e_qp;

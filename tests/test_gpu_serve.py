@@ -11,6 +11,8 @@ import numpy as np
 import pytest
 
 import paper_2412_17132_amd as gwc
+from oracle import cumulant as OC
+from oracle import sigma as OS
 from paper_2412_17132_amd.serve import ResidentSystem, Server
 from workloads import EV_PER_HA, serving_request_config, system_from_config
 
@@ -30,6 +32,42 @@ def _submit(srv, rs, s, core, precision="fp64", mode="decoupled"):
     return srv.submit(rs, core, s.omega_imag, s.w_imag, s.omega_real[core], s.eta, mode=mode,
                       precision=precision, n_t=2 ** 14, d_omega=0.01 / EV_PER_HA, n_out=2000,
                       omega_out_min_rel=-15 / EV_PER_HA)
+
+
+@pytest.mark.parametrize("batch_bytes", [0, 64 << 20], ids=["default_plan", "64MB_batches"])
+def test_served_requests_match_oracle(batch_bytes):
+    """One served request per molecule, all in flight together (DECOUPLED +
+    A(w)), against the oracle run end to end for that core state: Sigma^c(eps_n),
+    Sigma^x, E_QP and Im Sigma^dec of oracle.sigma_core (Eqs. cd_terms,
+    cd_sigma_imaginary_decoupled, QPGWC), then A(w) and Z of
+    oracle.spectral_cumulant on the oracle's own Im Sigma^dec and E_QP, all to
+    1e-9.  With 64 MB batches the larger molecules' screening runs in several
+    launches per axis."""
+    mols = _molecules()
+    res = [ResidentSystem.from_system(s) for s in mols]
+    srv = Server(n_slots=3, hbm_budget_bytes=8 << 30, batch_bytes=batch_bytes)
+    picks = [(i, mols[i].n_core - 1) for i in range(len(mols))]
+    print(f"case served vs oracle, batch_bytes={batch_bytes}, picks {picks}", flush=True)
+    tickets = [(i, c, _submit(srv, res[i], mols[i], c)) for i, c in picks]
+    got = [(i, c, srv.wait(t)) for i, c, t in tickets]
+    srv.close()
+    for r in res:
+        r.close()
+    for i, c, r in got:
+        s = mols[i]
+        n = int(s.core_idx[c])
+        ref = OS.sigma_core(s.eps, s.occ, s.M_oo, s.M_ov, s.core_idx[c:c + 1], s.omega_imag, s.w_imag,
+                            s.omega_real[c:c + 1], s.eta, mode="decoupled")
+        e_ref = float(ref["e_qp"][0])
+        assert abs(r["e_qp"] - e_ref) <= 1e-9 * abs(e_ref), (i, c)
+        assert abs(r["sigma_x"] - ref["sigma_x"][0]) <= 1e-9 * abs(ref["sigma_x"][0]), (i, c)
+        assert abs(r["sigma_c_eps"] - ref["sigma_c_eps"][0]) <= 1e-9 * abs(ref["sigma_c_eps"][0]), (i, c)
+        im_ref = ref["im_sigma_dec"][0]
+        assert np.max(np.abs(r["im_sigma_dec"] - im_ref)) <= 1e-9 * np.max(np.abs(im_ref)), (i, c)
+        A_ref, Z_ref, _ = OC.spectral_cumulant(s.omega_real[c], im_ref, float(s.eps[n]), e_ref, s.eta,
+                                               2 ** 14, 0.01 / EV_PER_HA, 2000, e_ref - 15 / EV_PER_HA)
+        assert np.max(np.abs(r["A"] - A_ref)) <= 1e-9 * np.max(np.abs(A_ref)), (i, c)
+        assert abs(r["z"][0] - Z_ref) <= 1e-12, (i, c)
 
 
 def test_resident_matches_one_shot():

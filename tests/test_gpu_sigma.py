@@ -122,6 +122,25 @@ def test_run_to_run_bitwise():
             assert np.array_equal(a[k], b[k]), k
 
 
+def test_batch_loop_past_the_first_launch(monkeypatch):
+    """The batch loop of the screening tasks beyond its first launch, with a
+    ragged last launch on both axes: c1 FULL with at most 7 tasks per launch
+    (575 residue tasks = 82 launches of 7 and one of 1; 24 imaginary nodes =
+    3 launches of 7 and one of 3) matches the oracle to 1e-9 and is bitwise
+    equal to the run that puts each axis in one launch."""
+    s = system_from_config(CONFIGS["c1"])
+    print("c1 full, default batch", flush=True)
+    one = _run(s)
+    monkeypatch.setenv("GWC_MAX_BATCH", "7")
+    print("c1 full, GWC_MAX_BATCH=7", flush=True)
+    many = _run(s)
+    monkeypatch.delenv("GWC_MAX_BATCH")
+    _compare(many, OS.sigma_core_system(s))
+    for k in one:
+        if one[k] is not None:
+            assert np.array_equal(one[k], many[k]), k
+
+
 def test_c2_size_sampled():
     """Benzene-sized system (N_aux = 1200, N_ov = 5859, all 6 cores) with the
     batch size of the benchmark; the oracle checks sampled points."""

@@ -107,3 +107,30 @@ def test_wac_c1_quasiparticle_energy():
     cd = OS.sigma_core_system(s)
     assert np.max(np.abs(out["e_qp"] - cd["e_qp"])) * EV_PER_HA < 1e-3
 
+
+
+def test_wac_breakdown_returns_factorization_error():
+    """A core state whose RI coefficients vanish (M_nm = 0 for every m) has
+    W^c_nm = 0 at every reference point, so Thiele's reciprocal differences
+    divide by zero: CD-WAC returns GWC_ERR_FACTORIZATION (-5) as a status, with
+    a message, and the library stays usable (contour deformation on the same
+    system then gives Sigma^c = 0 exactly, and CD-WAC on an intact system
+    succeeds)."""
+    s = system_from_config(small_config(n_occ=4, n_virt=7, n_aux=30, n_core=1, n_real=5, seed=61))
+    s.M_oo = s.M_oo.copy()
+    s.M_ov = s.M_ov.copy()
+    s.M_oo[:, 0, :] = 0.0
+    s.M_oo[:, :, 0] = 0.0
+    s.M_ov[:, 0, :] = 0.0
+    p = gwc.wac_paper_settings(n_core_pts=20, n_val_pts=20)
+    print("case zero core coefficients, CD-WAC", flush=True)
+    with pytest.raises(gwc.GwcError) as ei:
+        _gpu(s, p)
+    assert ei.value.status == -5
+    assert "continued-fraction" in str(ei.value)
+    out = gwc.gwc_sigma_core(s.eps, s.occ, s.M_oo, s.M_ov, s.core_idx, s.omega_imag, s.w_imag,
+                             s.omega_real, s.eta, mode="full")
+    assert np.all(out["sigma_c"] == 0.0) and np.all(out["sigma_c_eps"] == 0.0)
+    good = system_from_config(small_config(n_occ=4, n_virt=7, n_aux=30, n_core=1, n_real=5, seed=61))
+    ok = _gpu(good, p)
+    assert np.all(np.isfinite(ok["sigma_c"]))
