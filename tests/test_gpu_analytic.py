@@ -86,6 +86,7 @@ def test_analytic_c1_with_vxc():
     _compare(out, ref)
 
 
+@pytest.mark.blas_threads
 def test_analytic_c2_sampled():
     """Benzene-sized system (N_ov = 5859, 6 cores) at the size the bench times:
     every excitation energy, and Sigma^c / E_QP / A at 6 points per core."""

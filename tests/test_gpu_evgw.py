@@ -92,6 +92,7 @@ def test_evgw0_rejects_nonfinite_vv():
     assert ei.value.status_name == "GWC_ERR_NONFINITE"
 
 
+@pytest.mark.blas_threads
 def test_evgw0_c2_first_iteration_sampled():
     """Benzene-sized system (300 states, N_ov = 5859) at the size the bench
     times: the first iteration's energies (the G0W0 solutions from eps, each a

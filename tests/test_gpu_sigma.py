@@ -141,6 +141,7 @@ def test_batch_loop_past_the_first_launch(monkeypatch):
             assert np.array_equal(one[k], many[k]), k
 
 
+@pytest.mark.blas_threads
 def test_c2_size_sampled():
     """Benzene-sized system (N_aux = 1200, N_ov = 5859, all 6 cores) with the
     batch size of the benchmark; the oracle checks sampled points."""
