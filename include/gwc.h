@@ -234,6 +234,18 @@ typedef struct {
 int gwc_spectral_cumulant(const gwc_cumulant_args *args, double *A_out, double *z_out,
                           void *hip_stream);
 
+/* gwc_spectral_cumulant without device allocation, for callers that cannot
+ * allocate (code under stream capture, serving loops that forbid hipMalloc):
+ * the same arguments, kernels, results and errors, with every temporary in one
+ * library-owned device array per GPU (about 21 MB, held until the process
+ * ends) instead of the stream-ordered pool.  Limits: n_t <= 2^19 and
+ * n_real <= 2^15; larger sizes return GWC_ERR_SHAPE.  Inputs and outputs may
+ * be host or device memory, as for gwc_spectral_cumulant.  All calls on one GPU
+ * share that array: calls that overlap on one GPU (several host threads or
+ * streams) race and must be serialised by the caller. */
+int gwc_spectral_cumulant_noalloc(const gwc_cumulant_args *args, double *A_out, double *z_out,
+                                  void *hip_stream);
+
 /* Arguments of gwc_sigma_analytic.
  *   core_idx   [n_core]         occupied states n (each < n_occ)
  *   omega_real [n_core][n_real] real frequencies per core state, strictly increasing

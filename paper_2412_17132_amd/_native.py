@@ -31,6 +31,7 @@ PRECISIONS = {"fp64": 0, "bf16x3": 1, "fp16x3": 2, "fp8": 3}
 EXPORTED_SYMBOLS = (
     "gwc_sigma_core",
     "gwc_spectral_cumulant",
+    "gwc_spectral_cumulant_noalloc",
     "gwc_last_error",
     "gwc_version",
     "gwc_timing_enable",
@@ -188,6 +189,9 @@ def load(path: str = LIB_PATH):
     lib.gwc_sigma_core.restype = c_int
     lib.gwc_spectral_cumulant.argtypes = [POINTER(GwcCumulantArgs), c_void_p, c_void_p, c_void_p]
     lib.gwc_spectral_cumulant.restype = c_int
+    lib.gwc_spectral_cumulant_noalloc.argtypes = [POINTER(GwcCumulantArgs), c_void_p, c_void_p,
+                                                  c_void_p]
+    lib.gwc_spectral_cumulant_noalloc.restype = c_int
     lib.gwc_last_error.argtypes = []
     lib.gwc_last_error.restype = ctypes.c_char_p
     lib.gwc_version.argtypes = []

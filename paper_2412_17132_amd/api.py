@@ -231,6 +231,22 @@ def gwc_spectral_cumulant(omega_real, im_sigma, eps_n, e_qp, eta, n_t, d_omega, 
     return A_out, z_out
 
 
+def gwc_spectral_cumulant_noalloc(omega_real, im_sigma, eps_n, e_qp, eta, n_t, d_omega, n_out,
+                                  omega_out_min, A_out, z_out=None, stream=None):
+    """gwc_spectral_cumulant_noalloc: the same spectral function with no device
+    allocation in the library (n_t <= 2^19, n_real <= 2^15).  The caller passes
+    the outputs (A_out [n_out], z_out [2] or None); returns (A_out, z_out)."""
+    lib = N.load()
+    keep: list = []
+    n_real = int(omega_real.shape[0])
+    args = N.GwcCumulantArgs(n_real, _as_arg(omega_real, "f8", keep), _as_arg(im_sigma, "f8", keep),
+                             float(eps_n), float(e_qp), float(eta), int(n_t), float(d_omega),
+                             int(n_out), float(omega_out_min))
+    N.check(lib.gwc_spectral_cumulant_noalloc(args, _as_out(A_out), _as_out(z_out),
+                                              _stream_handle(stream)))
+    return A_out, z_out
+
+
 def to_device(system, device="cuda"):
     """Device-resident copies (torch tensors) of a system's arrays."""
     torch = _torch()
