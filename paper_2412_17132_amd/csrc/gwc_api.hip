@@ -69,9 +69,9 @@ struct PendingTiming {
   hipEvent_t a, b;
   double flops;
 };
-constexpr int kNumTimed = 5;
+constexpr int kNumTimed = 6;
 const char *const kTimedKernels[kNumTimed] = {"pi_build_f64", "lu_bordered", "pi_build_mixed",
-                                              "jacobi_apply", "jacobi_pairs"};
+                                              "jacobi_apply", "jacobi_pairs", "ldlt_bordered"};
 std::mutex g_timing_mutex;
 std::atomic<bool> g_timing{false};
 TimerStat g_stats[kNumTimed];
@@ -408,10 +408,22 @@ BatchPlan plan_batch(const ResidentSystem &rs, size_t T, int R, size_t batch_byt
   return p;
 }
 
+// Factorisation of the bordered matrices: LDL^T without pivoting (default;
+// 1 - Pi(z) is complex symmetric with a positive semidefinite imaginary part,
+// or real SPD on the imaginary axis) or the partial-pivoting LU
+// (GWC_FACTORIZATION=lu, and the retry of any matrix whose LDL^T met an
+// exactly zero pivot).
+enum Factorization { FACT_LDLT = 0, FACT_LU = 1 };
+
+Factorization default_factorization() {
+  const char *e = std::getenv("GWC_FACTORIZATION");
+  return (e && std::string(e) == "lu") ? FACT_LU : FACT_LDLT;
+}
+
 // Runs every task of `tl` (border width R) and writes W into W_out.
 void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, const TaskList &tl,
                    int R, double2 *W_out, std::vector<int> &status_all, hipStream_t s,
-                   size_t batch_bytes) {
+                   size_t batch_bytes, Factorization fact = default_factorization()) {
   const size_t T = tl.size();
   if (T == 0) return;
   const int N = rs.N;
@@ -426,7 +438,7 @@ void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, c
 
   DevBuf dG(s), dchr(s), dchi(s), dz(s), dn(s), dm(s), dob(s), dos(s), dbb(s), dst(s), dscr(s), dts(s);
   dG.alloc(plan.mat_bytes * F);
-  dscr.alloc(lu_scratch_bytes(F));
+  dscr.alloc(fact == FACT_LU ? lu_scratch_bytes(F) : ldlt_scratch_bytes(F));
   dts.alloc((size_t)F * sizeof(float));
   dchr.alloc((size_t)F * rs.ldl * sizeof(double));
   dchi.alloc((size_t)F * rs.ldl * sizeof(double));
@@ -465,11 +477,21 @@ void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, c
     launch_border(rs.d_Moo.as<double>(), rs.d_Mov.as<double>(), N, rs.no, rs.nv, n_d + t0, m_d + t0,
                   Fb, R, dG.as<double2>(), (long long)mat_elems, ldg, dbb.as<double>(), s);
     hipEvent_t eb = timing ? timing_mark(s) : nullptr;
-    HIPCHECK(launch_lu_bordered(dG.as<double2>(), (long long)mat_elems, ldg, N, R, Fb, dbb.as<double>(),
-                                ob_d + t0, os_d + t0, W_out, dst.as<int>() + t0, dscr.p, s));
+    if (fact == FACT_LU) {
+      HIPCHECK(launch_lu_bordered(dG.as<double2>(), (long long)mat_elems, ldg, N, R, Fb, dbb.as<double>(),
+                                  ob_d + t0, os_d + t0, W_out, dst.as<int>() + t0, dscr.p, s));
+    } else {
+      HIPCHECK(launch_ldlt_bordered(dG.as<double2>(), (long long)mat_elems, ldg, N, R, Fb,
+                                    dbb.as<double>(), ob_d + t0, os_d + t0, W_out, dst.as<int>() + t0,
+                                    dscr.p, s));
+    }
     if (timing) {
-      const double fl = Fb * ((8.0 / 3.0) * N * (double)N * N + 8.0 * (double)N * N * R);
-      pending.push_back({1, eb, timing_mark(s), fl});
+      // algorithmic flops: LU (8/3) N^3 + 8 N^2 R; LDL^T half the elimination
+      // and one border side, (4/3) N^3 + 4 N^2 R
+      const double nn = (double)N * N;
+      const double fl = fact == FACT_LU ? Fb * ((8.0 / 3.0) * nn * N + 8.0 * nn * R)
+                                        : Fb * ((4.0 / 3.0) * nn * N + 4.0 * nn * R);
+      pending.push_back({fact == FACT_LU ? 1 : 5, eb, timing_mark(s), fl});
     }
     HIPCHECK(hipGetLastError());
   }
@@ -477,6 +499,26 @@ void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, c
   HIPCHECK(hipMemcpyAsync(st.data(), dst.p, T * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
   timing_resolve(pending);
+  if (fact == FACT_LDLT) {
+    // a zero pivot of the unpivoted elimination (Im(1 - Pi) vanishing in
+    // floating point): those matrices again with partial pivoting
+    TaskList retry;
+    std::vector<size_t> which;
+    for (size_t t = 0; t < T; ++t)
+      if (st[t]) {
+        retry.z.push_back(tl.z[t]);
+        retry.n.push_back(tl.n[t]);
+        retry.m.push_back(tl.m[t]);
+        retry.out_base.push_back(tl.out_base[t]);
+        retry.out_stride.push_back(tl.out_stride[t]);
+        which.push_back(t);
+      }
+    if (!which.empty()) {
+      std::vector<int> st_lu;
+      run_screening(rs, mx, precision, retry, R, W_out, st_lu, s, batch_bytes, FACT_LU);
+      for (size_t k = 0; k < which.size(); ++k) st[which[k]] = st_lu[k];
+    }
+  }
   status_all.insert(status_all.end(), st.begin(), st.end());
 }
 

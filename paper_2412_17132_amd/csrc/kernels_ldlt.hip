@@ -1,0 +1,291 @@
+// Screened-interaction elements from a bordered LDL^T factorisation without
+// pivoting (FP64 complex symmetric).
+//
+// 1 - Pi(z) is complex symmetric (Pi = L diag(chi) L^T).  On the real axis,
+// z = x + i eta with x > 0, every Im chi_ia < 0, so Im(1 - Pi) = L |Im chi| L^T
+// is positive semidefinite; on the imaginary axis 1 - Pi is real symmetric
+// positive definite.  Then v^T (1 - Pi) v has a positive imaginary (or real)
+// part for every real nonzero v restricted to a leading block, so every
+// leading principal minor is nonsingular and the elimination needs no
+// pivoting.  The bordered matrix
+//
+//        [ 1 - Pi(z)   B ]
+//   M =  [ B^T         0 ]      (symmetric, order n = N + R)
+//
+// is factored L D L^T over its first N columns; the border block then holds
+// the Schur complement -B^T (1 - Pi)^-1 B, and W^c = -S_rr - b^T b as for the
+// LU (launch_bordered_finish).  Only the lower triangle is read.
+//
+// Right-looking, 64-column steps, per step and batch of matrices:
+//   D  one workgroup per matrix: the 64 x 64 diagonal block A11 = L11 D1 L11^T
+//      in LDS (64 dependent rank-1 steps), then L11^-1 (unit lower) and D1^-1
+//      to the scratch;
+//   T  one workgroup per (matrix, 64-row block below the panel): W = A21 L11^-T
+//      on MFMA; the column part becomes L21 = W D1^-1 and the row part (upper
+//      triangle, otherwise unused) W^T = D1 L21^T, so that
+//   G  the trailing update A22 -= L21 (W^T) = L21 D1 L21^T is the LU's
+//      trailing kernel restricted to the tiles on or below the diagonal
+//      (half the tiles; border-border tiles off the diagonal skipped).
+// Up to LDLT_GROUP panels share one trailing update (K = 64 LDLT_GROUP), a
+// later panel of a group first receiving the group's earlier panels on its own
+// 64 columns.  Against the partial-pivoting LU this halves the trailing flops
+// and removes the pivot searches, interchanges and row moves.
+#include "gwc_internal.h"
+
+namespace gwc {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int NB = 64;
+constexpr int NXCD = 8;
+constexpr int LDLT_GROUP = 3;
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zsub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ double2 zinv(double2 d) {
+  // 1/d with scaling by the larger component (Smith)
+  if (fabs(d.x) >= fabs(d.y)) {
+    const double r = d.y / d.x, den = d.x + d.y * r;
+    return make_double2(1.0 / den, -r / den);
+  }
+  const double r = d.x / d.y, den = d.x * r + d.y;
+  return make_double2(r / den, -1.0 / den);
+}
+
+// Workgroup -> (matrix, item), all items of a matrix on one XCD.
+__device__ __forceinline__ bool xcd_item(int wg, int items, int F, int &f, int &item) {
+  const int x = wg % NXCD, j = wg / NXCD;
+  f = (j / items) * NXCD + x;
+  item = j - (j / items) * items;
+  return f < F;
+}
+
+// D: one workgroup (256 threads) per matrix.  X = the lower triangle of the
+// kb x kb diagonal block (identity beyond kb).  Step t: every row i > t takes
+// X[i][j] -= (X[i][t] / d_t) X[j][t] for t < j <= i, then column t is scaled
+// by 1/d_t.  Thread tid owns row tid / 4 and the columns j = tid % 4 (mod 4).
+// Afterwards X holds L11 (unit, strictly lower) and D1 (diagonal); D1 and L11
+// go back to the block, D1^-1 and L11^-1 (the LU's right-looking in-place
+// inversion) to the scratch, zero-padded beyond kb.
+__global__ void __launch_bounds__(256)
+ldlt_diag_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int K0,
+                 double2 *__restrict__ linv_g, double2 *__restrict__ dinv_g, int *__restrict__ status) {
+  __shared__ double2 X[NB][NB + 1];
+  __shared__ int zero;
+  const int f = blockIdx.x, tid = threadIdx.x;
+  double2 *A = G + (long long)f * gs;
+  const int kb = min(NB, N - K0);
+  if (tid == 0) zero = 0;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, j = idx - i * NB;
+    X[i][j] = (i < kb && j <= i) ? A[(long long)(K0 + i) * ldg + K0 + j]
+                                 : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const int i = tid >> 2, j0 = tid & 3;
+  for (int t = 0; t < kb; ++t) {
+    const double2 d = X[t][t];
+    const bool dz = d.x == 0.0 && d.y == 0.0;
+    const double2 inv = dz ? make_double2(0.0, 0.0) : zinv(d);
+    if (dz && tid == 0) zero = 1;
+    const double2 l = zmul(X[i][t], inv);
+    if (i > t) {
+      int j = t + 1 + ((j0 - (t + 1)) & 3);
+      for (; j <= i; j += 4) X[i][j] = zsub(X[i][j], zmul(l, X[j][t]));
+    }
+    __syncthreads();
+    if (i > t && (t & 3) == j0) X[i][t] = l;
+    __syncthreads();
+  }
+  // D1^-1 and the factored block
+  if (tid < NB) {
+    const double2 d = X[tid][tid];
+    dinv_g[(long long)f * NB + tid] =
+        (tid < kb && !(d.x == 0.0 && d.y == 0.0)) ? zinv(d) : make_double2(0.0, 0.0);
+  }
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx / NB, c = idx - r * NB;
+    if (r < kb && c <= r) A[(long long)(K0 + r) * ldg + K0 + c] = X[r][c];
+  }
+  __syncthreads();
+  if (tid < NB) X[tid][tid] = make_double2(1.0, 0.0);
+  __syncthreads();
+  // L11^-1 in place: at step t every row i > t takes X[i][j] -= L[i][t] X[t][j]
+  // for j < t and X[i][t] = -L[i][t] (row t of X is final by then)
+  for (int t = 0; t < NB - 1; ++t) {
+    const double2 l = X[i][t];
+    __syncthreads();
+    if (i > t) {
+      for (int j = j0; j < t; j += 4) X[i][j] = zsub(X[i][j], zmul(l, X[t][j]));
+      if ((t & 3) == j0) X[i][t] = make_double2(-l.x, -l.y);
+    }
+    __syncthreads();
+  }
+  double2 *Li = linv_g + (long long)f * NB * NB;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx / NB, c = idx - r * NB;
+    Li[idx] = (r < kb && c < kb) ? X[r][c] : make_double2(0.0, 0.0);
+  }
+  if (tid == 0 && zero) status[f] = 1;
+}
+
+// T: one workgroup (8 waves) per (matrix, 64-row block of rows r0.. below the
+// panel).  Waves 0-3 form W = A21 L11^-T (32 x 32 each) and store the column
+// part L21 = W D1^-1; waves 4-7 form W^T = L11^-1 A21^T and store it as the
+// row part A[K0 + k][r] (coalesced along r).  Every read of A21 precedes the
+// barrier before the first store.  Operands come straight from memory
+// (A21 and L11^-1 of a matrix are shared in its XCD's L2); rows >= n and
+// columns >= kb contribute zero.  MFMA layouts: A[l%16][l/16],
+// B[l/16][l%16], D[4r + l/16][l%16].
+__global__ void __launch_bounds__(512)
+ldlt_trsm_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0, int F,
+                 int nblk, const double2 *__restrict__ linv_g, const double2 *__restrict__ dinv_g) {
+  int f, blk;
+  if (!xcd_item(blockIdx.x, nblk, F, f, blk)) return;
+  const int n = N + R;
+  const int kb = min(NB, N - K0);
+  const int r0 = K0 + kb + NB * blk;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool transposed = wave >= 4;
+  const int w4 = wave & 3;
+  const int wr = (w4 >> 1) * 32, wc = (w4 & 1) * 32;
+  double2 *A = G + (long long)f * gs;
+  const double2 *Li = linv_g + (long long)f * NB * NB;
+
+  d4 re[2][2], im[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      re[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      im[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int kk = 0; kk < kb; kk += 4) {
+    const int k = kk + lk;
+    double2 av[2], bv[2];
+    if (!transposed) {
+      // A operand: A21 rows (r0 + wr + 16a + li), column K0 + k;
+      // B operand: L11^-T [k][c] = L11^-1 [c][k], c = wc + 16b + li
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int row = r0 + wr + 16 * a + li;
+        av[a] = (row < n && k < kb) ? A[(long long)row * ldg + K0 + k] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Li[(wc + 16 * b + li) * NB + k];
+    } else {
+      // A operand: L11^-1 rows (wr + 16a + li), column k;
+      // B operand: A21^T [k][r] = A21[r][k], r = r0 + wc + 16b + li
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = Li[(wr + 16 * a + li) * NB + k];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int row = r0 + wc + 16 * b + li;
+        bv[b] = (row < n && k < kb) ? A[(long long)row * ldg + K0 + k] : make_double2(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, re[a][b], 0, 0, 0);
+        re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].y, re[a][b], 0, 0, 0);
+        im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, im[a][b], 0, 0, 0);
+        im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, im[a][b], 0, 0, 0);
+      }
+  }
+  __syncthreads();  // all of A21 has been read
+  if (!transposed) {
+    const double2 *Di = dinv_g + (long long)f * NB;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int k = wc + 16 * b + li;
+      const double2 di = Di[k];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + wr + 16 * a + 4 * r + lk;
+          if (row < n && k < kb)
+            A[(long long)row * ldg + K0 + k] = zmul(make_double2(re[a][b][r], im[a][b][r]), di);
+        }
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = wr + 16 * a + 4 * r + lk;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int col = r0 + wc + 16 * b + li;
+          if (k < kb && col < n)
+            A[(long long)(K0 + k) * ldg + col] = make_double2(re[a][b][r], im[a][b][r]);
+        }
+      }
+  }
+}
+
+struct LdltLaunch {
+  double2 *G;
+  long long gs;
+  int ldg, N, R, F, fgroups;
+  double2 *linv, *dinv;
+  int *status;
+  hipStream_t s;
+
+  void diag_trsm(int K0) const {
+    const int n = N + R;
+    const int kb = min(NB, N - K0);
+    ldlt_diag_kernel<<<F, 256, 0, s>>>(G, gs, ldg, N, K0, linv, dinv, status);
+    const int nblk = (n - K0 - kb + NB - 1) / NB;
+    if (nblk > 0)
+      ldlt_trsm_kernel<<<NXCD * fgroups * nblk, 512, 0, s>>>(G, gs, ldg, N, R, K0, F, nblk, linv, dinv);
+  }
+};
+
+}  // namespace
+
+size_t ldlt_scratch_bytes(int F) {
+  return (size_t)F * (NB * NB + NB) * sizeof(double2) + 256;
+}
+
+hipError_t launch_ldlt_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
+                                const double *bb, const long long *out_base, const int *out_stride,
+                                double2 *W_out, int *status, void *scratch, hipStream_t stream) {
+  const int n = N + R;
+  double2 *linv = static_cast<double2 *>(scratch);
+  double2 *dinv = linv + (size_t)F * NB * NB;
+  launch_zero_status(status, F, stream);
+  const LdltLaunch L{G, g_stride, ldg, N, R, F, (F + NXCD - 1) / NXCD, linv, dinv, status, stream};
+  int K0 = 0;
+  while (K0 < N) {
+    const int g = min(LDLT_GROUP, (N - K0) / NB);
+    if (g >= 2) {
+      const int a = K0, e = K0 + g * NB;
+      for (int p = 0; p < g; ++p) {
+        const int b = a + p * NB;
+        if (p > 0) launch_trailing_update(G, g_stride, ldg, N, R, F, b, b, b + NB, a, p * NB, false, stream);
+        L.diag_trsm(b);
+      }
+      launch_trailing_update(G, g_stride, ldg, N, R, F, e, e, n, a, g * NB, true, stream);
+      K0 = e;
+    } else {
+      const int kend = min(K0 + NB, N);
+      L.diag_trsm(K0);
+      launch_trailing_update(G, g_stride, ldg, N, R, F, kend, kend, n, K0, kend - K0, true, stream);
+      K0 = kend;
+    }
+  }
+  launch_bordered_finish(G, g_stride, ldg, N, R, F, bb, out_base, out_stride, W_out, stream);
+  return hipGetLastError();
+}
+
+}  // namespace gwc

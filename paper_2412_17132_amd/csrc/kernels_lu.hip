@@ -535,13 +535,27 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int K0
 // come straight from memory (the panels of one matrix are shared in its XCD's
 // L2), so the K loop has no barriers.  The operands of the next k step are
 // loaded into a second register set while the MFMAs of the current one run.
+// LOWER: the grid holds only the tiles on or below the diagonal of a square
+// range (row0 == col0, mt_r == mt_c), tile t -> (ti, tj) with
+// t = ti (ti + 1) / 2 + tj, tj <= ti (the symmetric factorisation's update).
+template <bool LOWER>
 __global__ void __launch_bounds__(256, 3)
 lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int F, int row0,
                    int col0, int col_end, int mt_r, int mt_c, int kstart, int klen) {
   int f, tile;
-  if (!xcd_map(blockIdx.x, mt_r * mt_c, F, f, tile)) return;
+  const int items = LOWER ? mt_r * (mt_r + 1) / 2 : mt_r * mt_c;
+  if (!xcd_map(blockIdx.x, items, F, f, tile)) return;
   const int n = N + R;
-  const int ti = tile / mt_c, tj = tile - ti * mt_c;
+  int ti, tj;
+  if (LOWER) {
+    ti = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+    while (ti * (ti + 1) / 2 > tile) --ti;
+    tj = tile - ti * (ti + 1) / 2;
+  } else {
+    ti = tile / mt_c;
+    tj = tile - ti * mt_c;
+  }
   const int ra = row0 + ti * 64, ca = col0 + tj * 64;
   if (ra >= N && ca >= N && (ra + 64 <= ca || ca + 64 <= ra)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -716,8 +730,8 @@ struct LuLaunch {
     const int n = N + R;
     const int mt_r = (n - r0 + 63) / 64, mt_c = (c1 - c0 + 63) / 64;
     if (mt_r < 1 || mt_c < 1) return;
-    lu_trailing_kernel<<<NXCD * fgroups * mt_r * mt_c, 256, 0, s>>>(G, gs, ldg, N, R, F, r0, c0, c1,
-                                                                     mt_r, mt_c, kstart, klen);
+    lu_trailing_kernel<false><<<NXCD * fgroups * mt_r * mt_c, 256, 0, s>>>(G, gs, ldg, N, R, F, r0, c0,
+                                                                            c1, mt_r, mt_c, kstart, klen);
   }
 };
 
@@ -763,6 +777,30 @@ hipError_t launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, in
   }
   lu_finish_kernel<<<F, 64, 0, stream>>>(G, g_stride, ldg, N, R, bb, out_base, out_stride, W_out);
   return hipGetLastError();
+}
+
+void launch_trailing_update(double2 *G, long long gs, int ldg, int N, int R, int F, int r0, int c0,
+                            int c1, int kstart, int klen, bool lower, hipStream_t s) {
+  const int n = N + R;
+  const int mt_r = (n - r0 + 63) / 64, mt_c = (c1 - c0 + 63) / 64;
+  if (mt_r < 1 || mt_c < 1) return;
+  const int fgroups = (F + NXCD - 1) / NXCD;
+  if (lower)
+    lu_trailing_kernel<true><<<NXCD * fgroups * (mt_r * (mt_r + 1) / 2), 256, 0, s>>>(
+        G, gs, ldg, N, R, F, r0, c0, c1, mt_r, mt_r, kstart, klen);
+  else
+    lu_trailing_kernel<false><<<NXCD * fgroups * mt_r * mt_c, 256, 0, s>>>(G, gs, ldg, N, R, F, r0, c0,
+                                                                            c1, mt_r, mt_c, kstart, klen);
+}
+
+void launch_bordered_finish(const double2 *G, long long gs, int ldg, int N, int R, int F,
+                            const double *bb, const long long *out_base, const int *out_stride,
+                            double2 *W_out, hipStream_t s) {
+  lu_finish_kernel<<<F, 64, 0, s>>>(G, gs, ldg, N, R, bb, out_base, out_stride, W_out);
+}
+
+void launch_zero_status(int *status, int F, hipStream_t s) {
+  zero_int_kernel<<<(F + 255) / 256, 256, 0, s>>>(status, F);
 }
 
 }  // namespace gwc

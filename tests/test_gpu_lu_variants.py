@@ -1,11 +1,14 @@
-"""GPU parity of the bordered LU at every panel shape it dispatches.
+"""GPU parity of both factorisations of the bordered matrices at wide borders.
 
-The batched LU keeps each panel row-block in registers, with a register
-layout chosen by the bordered order n = N_aux + R (R = N_basis border vectors
-on the imaginary axis).  A small N_aux with a wide border reaches every layout
-up to the largest supported order at little oracle cost (the oracle solves
-N_aux x N_aux systems); N_aux = 150 gives three outer steps, the last one
-ragged.  Orders above the largest supported one are refused.
+The default LDL^T (no pivoting) and the partial-pivoting LU
+(GWC_FACTORIZATION=lu).  The batched LU keeps each panel row-block in
+registers, with a register layout chosen by the bordered order n = N_aux + R
+(R = N_basis border vectors on the imaginary axis).  A small N_aux with a wide
+border reaches every layout up to the largest supported order at little
+oracle cost (the oracle solves N_aux x N_aux systems); N_aux = 150 gives three
+outer steps, the last one ragged, and for the LDL^T a border block of up to
+190 tile rows whose off-diagonal tiles are skipped.  Orders above the largest
+supported one are refused.
 """
 import numpy as np
 import pytest
@@ -25,12 +28,14 @@ MAX_ORDER = 24 * 512
 VIRT = [1800, 2800, 3800, 5900, 7900, 12000]
 
 
+@pytest.mark.parametrize("fact", ["ldlt", "lu"])
 @pytest.mark.parametrize("n_virt", VIRT, ids=[f"order{N_AUX + 3 + v}" for v in VIRT])
-def test_wide_border_orders(n_virt):
+def test_wide_border_orders(n_virt, fact, monkeypatch):
     assert N_AUX + 3 + n_virt <= MAX_ORDER
+    monkeypatch.setenv("GWC_FACTORIZATION", fact)
     s = system_from_config(small_config(name="wide", n_occ=3, n_virt=n_virt, n_aux=N_AUX, n_core=1,
                                         n_imag=4, n_real=3, seed=300 + n_virt % 97))
-    print(f"case n_aux={N_AUX} n_basis={s.n_basis} order={N_AUX + s.n_basis}", flush=True)
+    print(f"case {fact} n_aux={N_AUX} n_basis={s.n_basis} order={N_AUX + s.n_basis}", flush=True)
     dev = torch.device("cuda:0")
     d = gwc.to_device(s, dev)
     out = gwc.gwc_sigma_core(d["eps"], d["occ"], d["M_oo"], d["M_ov"], d["core_idx"],

@@ -141,6 +141,23 @@ def test_batch_loop_past_the_first_launch(monkeypatch):
             assert np.array_equal(one[k], many[k]), k
 
 
+def test_ldlt_and_lu_agree_with_the_oracle(monkeypatch):
+    """Both factorisations of the bordered matrices (the default LDL^T without
+    pivoting and the partial-pivoting LU) on c1 FULL: each matches the oracle
+    (which uses Cholesky and the pivoted LU) to 1e-9, and they agree with each
+    other to rounding."""
+    s = system_from_config(CONFIGS["c1"])
+    ref = OS.sigma_core_system(s)
+    got = {}
+    for fact in ("ldlt", "lu"):
+        monkeypatch.setenv("GWC_FACTORIZATION", fact)
+        print(f"c1 full, factorisation {fact}", flush=True)
+        got[fact] = _run(s)
+        _compare(got[fact], ref)
+    a, b = _cplx(got["ldlt"]["sigma_c"]), _cplx(got["lu"]["sigma_c"])
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
 @pytest.mark.blas_threads
 def test_c2_size_sampled():
     """Benzene-sized system (N_aux = 1200, N_ov = 5859, all 6 cores) with the
