@@ -402,8 +402,9 @@ BatchPlan plan_batch(const ResidentSystem &rs, size_t T, int R, size_t batch_byt
   fb = std::min<size_t>(fb, (size_t)max_batch_tasks());
   fb = std::min(fb, T);
   p.F = (int)fb;
-  p.bytes = fb * p.mat_bytes + lu_scratch_bytes((int)std::max<size_t>(fb, 1)) +
-            fb * (2 * (size_t)rs.ldl * sizeof(double) + R * sizeof(double) + sizeof(float)) +
+  p.bytes = fb * p.mat_bytes + std::max(lu_scratch_bytes((int)std::max<size_t>(fb, 1)),
+                                          ldlt_scratch_bytes((int)std::max<size_t>(fb, 1))) +
+            fb * (2 * (size_t)rs.ldl * (sizeof(double) + sizeof(float)) + R * sizeof(double) + sizeof(float)) +
             T * (sizeof(double2) + 3 * sizeof(int) + sizeof(long long) + sizeof(int)) + 4096;
   return p;
 }
@@ -437,7 +438,9 @@ void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, c
   const size_t mat_elems = (size_t)n * ldg;
 
   DevBuf dG(s), dchr(s), dchi(s), dz(s), dn(s), dm(s), dob(s), dos(s), dbb(s), dst(s), dscr(s), dts(s);
+  DevBuf dcf(s);
   dG.alloc(plan.mat_bytes * F);
+  if (precision != GWC_PREC_FP64) dcf.alloc((size_t)F * 2 * rs.ldl * sizeof(float));
   dscr.alloc(fact == FACT_LU ? lu_scratch_bytes(F) : ldlt_scratch_bytes(F));
   dts.alloc((size_t)F * sizeof(float));
   dchr.alloc((size_t)F * rs.ldl * sizeof(double));
@@ -465,7 +468,7 @@ void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, c
       launch_pi_build_mixed(precision, mx->Lf.as<float>(), mx->Bh.p, mx->Bl.p, rs.ldl, N,
                             dchr.as<double>(), dchi.as<double>(),
                             precision != GWC_PREC_BF16X3 ? mx->ics.as<float>() : nullptr,
-                            mx->acol.as<float>(), dts.as<float>(), Fb, mx->tiles.as<int2>(),
+                            mx->acol.as<float>(), dts.as<float>(), dcf.as<float>(), Fb, mx->tiles.as<int2>(),
                             mx->n_tiles, dG.as<double2>(), (long long)mat_elems, ldg, s);
     }
     if (timing) {

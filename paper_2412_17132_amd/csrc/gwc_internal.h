@@ -45,11 +45,12 @@ constexpr int mixed_tile_rows(int prec) { return prec == 3 ? 64 : 128; }
 void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, float *Lf,
                        void *Bhi, void *Blo, float *colscale, float *inv_colscale, float *acol,
                        hipStream_t stream);
+// chi_f32 is a workspace of F x 2 x ldl floats (the 16-bit forms' scaled FP32 chi).
 void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const void *Blo, int ldl,
                            int n_aux, const double *chi_re, const double *chi_im,
-                           const float *inv_colscale, const float *acol, float *tscale, int F,
-                           const int2 *tiles, int n_tiles, double2 *G, long long g_stride, int ldg,
-                           hipStream_t stream);
+                           const float *inv_colscale, const float *acol, float *tscale, float *chi_f32,
+                           int F, const int2 *tiles, int n_tiles, double2 *G, long long g_stride,
+                           int ldg, hipStream_t stream);
 void launch_border(const double *M_oo, const double *M_ov, int n_aux, int n_occ, int n_virt,
                    const int *task_n, const int *task_m, int F, int R, double2 *G,
                    long long g_stride, int ldg, double *bb, hipStream_t stream);

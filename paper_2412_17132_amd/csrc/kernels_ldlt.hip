@@ -21,8 +21,9 @@
 //      in LDS (64 dependent rank-1 steps), then L11^-1 (unit lower) and D1^-1
 //      to the scratch;
 //   T  one workgroup per (matrix, 64-row block below the panel): W = A21 L11^-T
-//      on MFMA; the column part becomes L21 = W D1^-1 and the row part (upper
-//      triangle, otherwise unused) W^T = D1 L21^T, so that
+//      on MFMA from the block staged in LDS; the column part becomes
+//      L21 = W D1^-1 and the row part (upper triangle, otherwise unused)
+//      W^T = D1 L21^T, so that
 //   G  the trailing update A22 -= L21 (W^T) = L21 D1 L21^T is the LU's
 //      trailing kernel restricted to the tiles on or below the diagonal
 //      (half the tiles; border-border tiles off the diagonal skipped).
@@ -135,17 +136,18 @@ ldlt_diag_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int K0,
   if (tid == 0 && zero) status[f] = 1;
 }
 
-// T: one workgroup (8 waves) per (matrix, 64-row block of rows r0.. below the
-// panel).  Waves 0-3 form W = A21 L11^-T (32 x 32 each) and store the column
-// part L21 = W D1^-1; waves 4-7 form W^T = L11^-1 A21^T and store it as the
-// row part A[K0 + k][r] (coalesced along r).  Every read of A21 precedes the
-// barrier before the first store.  Operands come straight from memory
-// (A21 and L11^-1 of a matrix are shared in its XCD's L2); rows >= n and
-// columns >= kb contribute zero.  MFMA layouts: A[l%16][l/16],
-// B[l/16][l%16], D[4r + l/16][l%16].
-__global__ void __launch_bounds__(512)
+// T: one workgroup (4 waves) per (matrix, 64-row block of rows r0.. below the
+// panel).  The A21 block is staged through LDS (coalesced rows); each wave
+// forms 16 rows of W = A21 L11^-T on MFMA (L11^-1 from L2, shared by the
+// matrix's workgroups on its XCD); W goes back to LDS and is stored twice,
+// both times along contiguous rows: the column part L21 = W D1^-1
+// (A[r][K0 + k]) and the row part W^T (A[K0 + k][r]).  Columns >= kb of the
+// block are zero in LDS, rows >= n are not stored.  MFMA layouts:
+// A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16].
+__global__ void __launch_bounds__(256)
 ldlt_trsm_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0, int F,
                  int nblk, const double2 *__restrict__ linv_g, const double2 *__restrict__ dinv_g) {
+  __shared__ double2 S[NB][NB + 1];
   int f, blk;
   if (!xcd_item(blockIdx.x, nblk, F, f, blk)) return;
   const int n = N + R;
@@ -153,83 +155,48 @@ ldlt_trsm_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, i
   const int r0 = K0 + kb + NB * blk;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const bool transposed = wave >= 4;
-  const int w4 = wave & 3;
-  const int wr = (w4 >> 1) * 32, wc = (w4 & 1) * 32;
   double2 *A = G + (long long)f * gs;
   const double2 *Li = linv_g + (long long)f * NB * NB;
-
-  d4 re[2][2], im[2][2];
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx / NB, k = idx - r * NB;
+    S[r][k] = (r0 + r < n && k < kb) ? A[(long long)(r0 + r) * ldg + K0 + k] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  d4 re[4], im[4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      re[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-      im[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    }
+  for (int b = 0; b < 4; ++b) {
+    re[b] = d4{0.0, 0.0, 0.0, 0.0};
+    im[b] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  const int wr = 16 * wave;
   for (int kk = 0; kk < kb; kk += 4) {
     const int k = kk + lk;
-    double2 av[2], bv[2];
-    if (!transposed) {
-      // A operand: A21 rows (r0 + wr + 16a + li), column K0 + k;
-      // B operand: L11^-T [k][c] = L11^-1 [c][k], c = wc + 16b + li
+    // A operand: rows wr + li of the block, column k; B operand:
+    // L11^-T [k][c] = L11^-1 [c][k] (zero for k >= kb), c = 16 b + li
+    const double2 av = S[wr + li][k];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int row = r0 + wr + 16 * a + li;
-        av[a] = (row < n && k < kb) ? A[(long long)row * ldg + K0 + k] : make_double2(0.0, 0.0);
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Li[(wc + 16 * b + li) * NB + k];
-    } else {
-      // A operand: L11^-1 rows (wr + 16a + li), column k;
-      // B operand: A21^T [k][r] = A21[r][k], r = r0 + wc + 16b + li
-#pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = Li[(wr + 16 * a + li) * NB + k];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int row = r0 + wc + 16 * b + li;
-        bv[b] = (row < n && k < kb) ? A[(long long)row * ldg + K0 + k] : make_double2(0.0, 0.0);
-      }
+    for (int b = 0; b < 4; ++b) {
+      const double2 bv = Li[(16 * b + li) * NB + k];
+      re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, re[b], 0, 0, 0);
+      re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, re[b], 0, 0, 0);
+      im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, im[b], 0, 0, 0);
+      im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, im[b], 0, 0, 0);
     }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, re[a][b], 0, 0, 0);
-        re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].y, re[a][b], 0, 0, 0);
-        im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, im[a][b], 0, 0, 0);
-        im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, im[a][b], 0, 0, 0);
-      }
   }
-  __syncthreads();  // all of A21 has been read
-  if (!transposed) {
-    const double2 *Di = dinv_g + (long long)f * NB;
+  __syncthreads();  // every wave has read its A21 rows
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int k = wc + 16 * b + li;
-      const double2 di = Di[k];
+  for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = r0 + wr + 16 * a + 4 * r + lk;
-          if (row < n && k < kb)
-            A[(long long)row * ldg + K0 + k] = zmul(make_double2(re[a][b][r], im[a][b][r]), di);
-        }
-    }
-  } else {
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = wr + 16 * a + 4 * r + lk;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int col = r0 + wc + 16 * b + li;
-          if (k < kb && col < n)
-            A[(long long)(K0 + k) * ldg + col] = make_double2(re[a][b][r], im[a][b][r]);
-        }
-      }
+    for (int r = 0; r < 4; ++r) S[wr + 4 * r + lk][16 * b + li] = make_double2(re[b][r], im[b][r]);
+  __syncthreads();
+  const double2 *Di = dinv_g + (long long)f * NB;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx / NB, k = idx - r * NB;
+    if (r0 + r < n && k < kb) A[(long long)(r0 + r) * ldg + K0 + k] = zmul(S[r][k], Di[k]);
+  }
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int k = idx / NB, r = idx - k * NB;
+    if (k < kb && r0 + r < n) A[(long long)(K0 + k) * ldg + r0 + r] = S[r][k];
   }
 }
 
@@ -247,7 +214,7 @@ struct LdltLaunch {
     ldlt_diag_kernel<<<F, 256, 0, s>>>(G, gs, ldg, N, K0, linv, dinv, status);
     const int nblk = (n - K0 - kb + NB - 1) / NB;
     if (nblk > 0)
-      ldlt_trsm_kernel<<<NXCD * fgroups * nblk, 512, 0, s>>>(G, gs, ldg, N, R, K0, F, nblk, linv, dinv);
+      ldlt_trsm_kernel<<<NXCD * fgroups * nblk, 256, 0, s>>>(G, gs, ldg, N, R, K0, F, nblk, linv, dinv);
   }
 };
 

@@ -561,6 +561,9 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  // the strictly upper quadrant of a diagonal tile is never read by the
+  // symmetric factorisation (the kernel has no barriers: a wave may leave)
+  if (LOWER && ra == ca && wr < wc) return;
   double2 *A = G + (long long)f * gs;
 
   // complex product in three real MFMA products (Gauss):

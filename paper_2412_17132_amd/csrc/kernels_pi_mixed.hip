@@ -297,6 +297,209 @@ pi_build_mixed_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__
       }
 }
 
+// Per-frequency FP32 chi with the column scales 2^-e_k and the frequency scale
+// 2^g folded in (the same float operations as the A operand needs), per K
+// chunk of 32 the 32 Re values then the 32 Im values: cf[f][k / 32][2][32].
+__global__ void __launch_bounds__(256)
+mixed_chi_kernel(const double *__restrict__ chi_re, const double *__restrict__ chi_im, int ldl,
+                 const float *__restrict__ inv_colscale, const float *__restrict__ tscale,
+                 float *__restrict__ cf) {
+  const int k = blockIdx.x * 256 + threadIdx.x, f = blockIdx.y;
+  if (k >= ldl) return;
+  const float s = inv_colscale ? inv_colscale[k] : 1.0f;
+  const float g = tscale ? tscale[f] : 1.0f;
+  float *o = cf + (long long)f * 2 * ldl + (k / MX_KC) * 2 * MX_KC + k % MX_KC;
+  o[0] = (float)chi_re[(long long)f * ldl + k] * s * g;
+  o[MX_KC] = (float)chi_im[(long long)f * ldl + k] * s * g;
+}
+
+// The 16-bit forms with the K chunks double-buffered in LDS.  One workgroup of
+// 16 waves per 128 x 256 tile and frequency; wave w covers rows 16 (w / 2) and
+// 128 columns from 128 (w % 2): 8 blocks of 16 x 16, Re and Im accumulators.
+// Each K chunk of 32 is fetched straight into LDS (global_load_lds, 16 bytes
+// per lane at wave base + 16 lane: no registers, no padding) while the chunk
+// before it is multiplied; the A rows (FP32 L) and the split B rows (64 bytes
+// per row) are each one load per wave.  The chunk's 64 FP32 chi values (Re,
+// Im) travel through a register of the first wave (loaded with the fetch,
+// stored after the multiply).  The reads of a chunk are conflict-free: 16 rows
+// x 64 (B) or 128 (A) bytes contiguous per wave.  Stage buffers are separate
+// __shared__ objects and the loop is unrolled by two, so each multiply names
+// one buffer and each fetch the other.
+// Raw buffer resources (base, no stride, size in bytes; the gfx9 format word):
+// the hardware returns zeros past the size instead of faulting.
+constexpr int BUF_FORMAT_WORD = 0x00020000;
+
+// One K chunk (columns kc .. kc + 32) of the tile's A rows and B rows into the
+// LDS stage, two 1 KB pieces of each buffer per wave: buffer_load ... lds with
+// a loop-invariant per-lane byte offset (voA, voB) and the chunk's offset as
+// the scalar offset.
+template <class T>
+__device__ __forceinline__ void mix_fetch(float *As, typename Mix<T>::E *Bh, typename Mix<T>::E *Bl,
+                                          float *C, __amdgpu_buffer_rsrc_t rA,
+                                          __amdgpu_buffer_rsrc_t rBh, __amdgpu_buffer_rsrc_t rBl,
+                                          __amdgpu_buffer_rsrc_t rC, const int (&voA)[2],
+                                          const int (&voB)[2], int kc, int wave, int lane) {
+  // the chunk's chi (64 floats) into this wave's own 1 KB of C (lanes 16 and
+  // up read what follows, or past the end of the buffer zeros: unused)
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rC, C + 256 * wave, 16, 16 * lane, kc * 8, 0, 0);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int q = 2 * wave + j;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rA, As + 256 * q, 16, voA[j], kc * 4, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rBh, Bh + 512 * q, 16, voB[j], kc * 2, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rBl, Bl + 512 * q, 16, voB[j], kc * 2, 0, 0);
+  }
+}
+
+// x = hi + lo for 8 values at once (vector conversions, round to nearest
+// even, packed in pairs by the hardware): the same values as Mix<T>::split.
+typedef float f8v __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f8v ld8(const float *p) {
+  const float4 a = reinterpret_cast<const float4 *>(p)[0];
+  const float4 b = reinterpret_cast<const float4 *>(p)[1];
+  return f8v{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+}
+
+template <class T>
+__device__ __forceinline__ void split8(f8v x, us8 &hi, us8 &lo) {
+  typedef T t8 __attribute__((ext_vector_type(8)));
+  const t8 h = __builtin_convertvector(x, t8);
+  const f8v r = x - __builtin_convertvector(h, f8v);
+  hi = __builtin_bit_cast(us8, h);
+  lo = __builtin_bit_cast(us8, __builtin_convertvector(r, t8));
+}
+
+// One wave's 16 rows against the 16 column blocks of a stage: blocks
+// b0 <= b < b1 only (wave-uniform bounds: blocks wholly below the diagonal or
+// past n_aux produce nothing that is stored, and the two waves of a SIMD
+// share its MFMA pipe, so skipping them shortens the tiles that cross the
+// diagonal).
+template <class T>
+__device__ __forceinline__ void mix_multiply(const float *As, const typename Mix<T>::E *Bh,
+                                             const typename Mix<T>::E *Bl, const float *C, int wr,
+                                             int li, int lq, int b0, int b1, f4 (&accr)[16],
+                                             f4 (&acci)[16]) {
+  using E = typename Mix<T>::E;
+  using V = typename Mix<T>::V;
+  if (b0 >= b1) return;
+  V arh, arl, aih, ail;
+  {
+    // 16-byte LDS reads only (a 32-byte read is split by the compiler into
+    // accesses it cannot tell apart from the fetch into the other stage, and
+    // it would then wait for that fetch)
+    const f8v cr = ld8(C + 8 * lq), ci = ld8(C + MX_KC + 8 * lq);
+    const f8v lv = ld8(As + (wr + li) * MX_KC + 8 * lq);
+    split8<T>(lv * cr, arh, arl);
+    split8<T>(lv * ci, aih, ail);
+  }
+  const E *bh_p = Bh + li * MX_KC + 8 * lq;
+  const E *bl_p = Bl + li * MX_KC + 8 * lq;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    if (b >= b0 && b < b1) {
+      const V bh = *reinterpret_cast<const V *>(bh_p + 16 * b * MX_KC);
+      const V bl = *reinterpret_cast<const V *>(bl_p + 16 * b * MX_KC);
+      accr[b] = Mix<T>::mfma(arh, bh, accr[b]);
+      accr[b] = Mix<T>::mfma(arh, bl, accr[b]);
+      accr[b] = Mix<T>::mfma(arl, bh, accr[b]);
+      acci[b] = Mix<T>::mfma(aih, bh, acci[b]);
+      acci[b] = Mix<T>::mfma(aih, bl, acci[b]);
+      acci[b] = Mix<T>::mfma(ail, bh, acci[b]);
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(512, 1)
+pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__restrict__ Bhi,
+                            const typename Mix<T>::E *__restrict__ Blo, int ldl, int n_aux,
+                            const float *__restrict__ cf_all, const float *__restrict__ tscale,
+                            const int2 *__restrict__ tiles, double2 *__restrict__ G,
+                            long long g_stride, int ldg) {
+  using E = typename Mix<T>::E;
+  static_assert(sizeof(E) == 2, "16-bit forms only");
+  // two stages as separate objects (the compiler then needs no wait between a
+  // fetch into one and the reads of the other)
+  __shared__ float A0[128 * MX_KC], A1[128 * MX_KC];
+  __shared__ E Bh0[MX_TC * MX_KC], Bh1[MX_TC * MX_KC], Bl0[MX_TC * MX_KC], Bl1[MX_TC * MX_KC];
+  __shared__ __attribute__((aligned(32))) float C0[8 * 256], C1[8 * 256];
+  // the wave index is uniform: in a scalar register, the LDS bases of the
+  // fetches can go to M0
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lq = lane >> 4;
+  const int2 tb = tiles[blockIdx.x];
+  const int P0 = tb.x * 128, Q0 = tb.y * MX_TC;
+  const int f = blockIdx.y;
+  const int wr = 16 * wave;
+  const float *cf = cf_all + (long long)f * 2 * ldl;
+  // column blocks this wave needs: some column >= its first row, and < n_aux;
+  // none when its rows are all padding
+  const int r_first = P0 + wr;
+  int b0 = (r_first - Q0 - 15 + 15) / 16;  // ceil((r_first - Q0 - 15) / 16) for r_first >= Q0
+  if (r_first - Q0 - 15 <= 0) b0 = 0;
+  const int b1 = r_first < n_aux ? min(16, (n_aux - Q0 + 15) / 16) : 0;
+  // this tile's 128 A rows and 256 B rows, as buffer resources; piece q of a
+  // buffer is rows 8q (A) or 16q (B) on, lane l at row + l / 8 (A: 8 lanes of
+  // 16 bytes per 128-byte row) or l / 4 (B: 4 lanes per 64-byte row)
+  const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(Lf + (long long)P0 * ldl), 0, 128 * ldl * 4, BUF_FORMAT_WORD);
+  const __amdgpu_buffer_rsrc_t rBh = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(Bhi + (long long)Q0 * ldl), 0, MX_TC * ldl * 2, BUF_FORMAT_WORD);
+  const __amdgpu_buffer_rsrc_t rBl = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(Blo + (long long)Q0 * ldl), 0, MX_TC * ldl * 2, BUF_FORMAT_WORD);
+  const __amdgpu_buffer_rsrc_t rC = __builtin_amdgcn_make_buffer_rsrc((void *)cf, 0, 2 * ldl * 4,
+                                                                      BUF_FORMAT_WORD);
+  int voA[2], voB[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int q = 2 * wave + j;
+    voA[j] = ((8 * q + (lane >> 3)) * ldl + (lane & 7) * 4) * 4;
+    voB[j] = ((16 * q + (lane >> 2)) * ldl + (lane & 3) * 8) * 2;
+  }
+
+  f4 accr[16], acci[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    accr[b] = f4{0.f, 0.f, 0.f, 0.f};
+    acci[b] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int nch = ldl / MX_KC;
+  mix_fetch<T>(A0, Bh0, Bl0, C0, rA, rBh, rBl, rC, voA, voB, 0, wave, lane);
+  int c = 0;
+  for (; c + 1 < nch; c += 2) {  // chunks c (stage 0) and c + 1 (stage 1)
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's fetch of chunk c has landed
+    __syncthreads();                // every wave's has; stage 1 is free again
+    mix_fetch<T>(A1, Bh1, Bl1, C1, rA, rBh, rBl, rC, voA, voB, (c + 1) * MX_KC, wave, lane);
+    mix_multiply<T>(A0, Bh0, Bl0, C0 + 256 * wave, wr, li, lq, b0, b1, accr, acci);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (c + 2 < nch) mix_fetch<T>(A0, Bh0, Bl0, C0, rA, rBh, rBl, rC, voA, voB, (c + 2) * MX_KC, wave, lane);
+    mix_multiply<T>(A1, Bh1, Bl1, C1 + 256 * wave, wr, li, lq, b0, b1, accr, acci);
+  }
+  if (c < nch) {  // an odd last chunk, in stage 0
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    mix_multiply<T>(A0, Bh0, Bl0, C0 + 256 * wave, wr, li, lq, b0, b1, accr, acci);
+  }
+
+  // upper triangle (col >= row) written with its mirror, as 1 - Pi
+  const double unscale = 1.0 / (double)(tscale ? tscale[f] : 1.0f);
+  double2 *Gf = G + (long long)f * g_stride;
+#pragma unroll
+  for (int b = 0; b < 16; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = P0 + wr + 4 * lq + r;
+      const int col = Q0 + 16 * b + li;
+      if (row < n_aux && col < n_aux && col >= row) {
+        const double pr = (double)accr[b][r] * unscale, pi = (double)acci[b][r] * unscale;
+        const double2 v = make_double2((row == col ? 1.0 : 0.0) - pr, -pi);
+        Gf[(long long)row * ldg + col] = v;
+        if (col != row) Gf[(long long)col * ldg + row] = v;
+      }
+    }
+}
+
 // ---------------------------------------------------------------------------
 void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, float *Lf,
                        void *Bhi, void *Blo, float *colscale, float *inv_colscale, float *acol,
@@ -324,25 +527,29 @@ void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, 
 
 void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const void *Blo, int ldl,
                            int n_aux, const double *chi_re, const double *chi_im,
-                           const float *inv_colscale, const float *acol, float *tscale, int F,
-                           const int2 *tiles, int n_tiles, double2 *G, long long g_stride, int ldg,
-                           hipStream_t stream) {
+                           const float *inv_colscale, const float *acol, float *tscale, float *chi_f32,
+                           int F, const int2 *tiles, int n_tiles, double2 *G, long long g_stride,
+                           int ldg, hipStream_t stream) {
   dim3 grid(n_tiles, F);
-  if (prec == 2) {
-    taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, Mix<_Float16>::TARGET, acol, tscale);
-    pi_build_mixed_kernel<_Float16><<<grid, 4 * mx_rows<_Float16>(), 0, stream>>>(
-        Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
-        n_aux, chi_re, chi_im, inv_colscale, tscale, tiles, G, g_stride, ldg);
-  } else if (prec == 3) {
+  if (prec == 3) {
     taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, Mix<e4m3>::TARGET, acol, tscale);
     pi_build_mixed_kernel<e4m3><<<grid, 4 * mx_rows<e4m3>(), 0, stream>>>(
         Lf, static_cast<const unsigned char *>(Bhi), static_cast<const unsigned char *>(Blo), ldl,
         n_aux, chi_re, chi_im, inv_colscale, tscale, tiles, G, g_stride, ldg);
-  } else {
-    pi_build_mixed_kernel<__bf16><<<grid, 4 * mx_rows<__bf16>(), 0, stream>>>(
-        Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
-        n_aux, chi_re, chi_im, nullptr, nullptr, tiles, G, g_stride, ldg);
+    return;
   }
+  const bool fp16 = prec == 2;
+  if (fp16) taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, Mix<_Float16>::TARGET, acol, tscale);
+  mixed_chi_kernel<<<dim3((ldl + 255) / 256, F), 256, 0, stream>>>(
+      chi_re, chi_im, ldl, fp16 ? inv_colscale : nullptr, fp16 ? tscale : nullptr, chi_f32);
+  if (fp16)
+    pi_build_mixed_async_kernel<_Float16><<<grid, 512, 0, stream>>>(
+        Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
+        n_aux, chi_f32, tscale, tiles, G, g_stride, ldg);
+  else
+    pi_build_mixed_async_kernel<__bf16><<<grid, 512, 0, stream>>>(
+        Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
+        n_aux, chi_f32, nullptr, tiles, G, g_stride, ldg);
 }
 
 }  // namespace gwc
