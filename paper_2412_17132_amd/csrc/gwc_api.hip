@@ -403,7 +403,7 @@ BatchPlan plan_batch(const ResidentSystem &rs, size_t T, int R, size_t batch_byt
   fb = std::min(fb, T);
   p.F = (int)fb;
   p.bytes = fb * p.mat_bytes + std::max(lu_scratch_bytes((int)std::max<size_t>(fb, 1)),
-                                          ldlt_scratch_bytes((int)std::max<size_t>(fb, 1))) +
+                                          ldlt_scratch_bytes((int)std::max<size_t>(fb, 1), rs.N)) +
             fb * (2 * (size_t)rs.ldl * (sizeof(double) + sizeof(float)) + R * sizeof(double) + sizeof(float)) +
             T * (sizeof(double2) + 3 * sizeof(int) + sizeof(long long) + sizeof(int)) + 4096;
   return p;
@@ -441,7 +441,7 @@ void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, c
   DevBuf dcf(s);
   dG.alloc(plan.mat_bytes * F);
   if (precision != GWC_PREC_FP64) dcf.alloc((size_t)F * 2 * rs.ldl * sizeof(float));
-  dscr.alloc(fact == FACT_LU ? lu_scratch_bytes(F) : ldlt_scratch_bytes(F));
+  dscr.alloc(fact == FACT_LU ? lu_scratch_bytes(F) : ldlt_scratch_bytes(F, N));
   dts.alloc((size_t)F * sizeof(float));
   dchr.alloc((size_t)F * rs.ldl * sizeof(double));
   dchi.alloc((size_t)F * rs.ldl * sizeof(double));

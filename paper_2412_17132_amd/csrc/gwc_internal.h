@@ -64,21 +64,23 @@ hipError_t launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, in
                               double2 *W_out, int *status, void *scratch, hipStream_t stream);
 
 // Pieces shared by the LU and the symmetric factorisation: the trailing update
-// A[r0.., c0..c1) -= A[r0.., K] A[K, c0..c1) over K = [kstart, kstart + klen)
-// (lower: only the tiles on or below the diagonal of the square range from
-// r0 = c0 to n), the border's W from the Schur complement, and clearing the
-// per-matrix status flags.
-void launch_trailing_update(double2 *G, long long gs, int ldg, int N, int R, int F, int r0, int c0,
-                            int c1, int kstart, int klen, bool lower, hipStream_t s);
+// of the symmetric factorisation, A[r0.., c0..c1) -= L[r0.., K] A[K, c0..c1)
+// over K = [kstart, kstart + klen) with L[r][k] = A[k][r] dinv[f dinv_ld + k]
+// (the panels' rows hold W^T = D L^T; lower: only the tiles on or below the
+// diagonal of the square range from r0 = c0 to n), the border's W from the
+// Schur complement, and clearing the per-matrix status flags.
+void launch_trailing_update_sym(double2 *G, long long gs, int ldg, int N, int R, int F, int r0,
+                                int c0, int c1, int kstart, int klen, bool lower,
+                                const double2 *dinv, int dinv_ld, hipStream_t s);
 void launch_bordered_finish(const double2 *G, long long gs, int ldg, int N, int R, int F,
                             const double *bb, const long long *out_base, const int *out_stride,
                             double2 *W_out, hipStream_t s);
 void launch_zero_status(int *status, int F, hipStream_t s);
 // Batched bordered LDL^T without pivoting (complex symmetric 1 - Pi with a
 // positive semidefinite imaginary part, or real SPD): same arguments and
-// outputs as launch_lu_bordered; `scratch` holds ldlt_scratch_bytes(F) bytes;
-// status[f] = 1 flags an exactly zero pivot.
-size_t ldlt_scratch_bytes(int F);
+// outputs as launch_lu_bordered; `scratch` holds ldlt_scratch_bytes(F, N)
+// bytes; status[f] = 1 flags an exactly zero pivot.
+size_t ldlt_scratch_bytes(int F, int N);
 hipError_t launch_ldlt_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
                                 const double *bb, const long long *out_base, const int *out_stride,
                                 double2 *W_out, int *status, void *scratch, hipStream_t stream);

@@ -18,15 +18,17 @@
 //
 // Right-looking, 64-column steps, per step and batch of matrices:
 //   D  one workgroup per matrix: the 64 x 64 diagonal block A11 = L11 D1 L11^T
-//      in LDS (64 dependent rank-1 steps), then L11^-1 (unit lower) and D1^-1
-//      to the scratch;
+//      in LDS (64 dependent rank-1 steps), then L11^-1 (unit lower) to the
+//      scratch and D1^-1 to the matrix's row of pivots' inverses;
 //   T  one workgroup per (matrix, 64-row block below the panel): W = A21 L11^-T
-//      on MFMA from the block staged in LDS; the column part becomes
-//      L21 = W D1^-1 and the row part (upper triangle, otherwise unused)
-//      W^T = D1 L21^T, so that
+//      on MFMA from the block staged in LDS, stored transposed in the row part
+//      (the upper triangle, otherwise unused): W^T = D1 L21^T, so that
 //   G  the trailing update A22 -= L21 (W^T) = L21 D1 L21^T is the LU's
 //      trailing kernel restricted to the tiles on or below the diagonal
-//      (half the tiles; border-border tiles off the diagonal skipped).
+//      (half the tiles; border-border tiles off the diagonal skipped), both
+//      operands read from the row part (L21[r][k] = W^T[k][r] / D[k]: the
+//      left operand's loads are coalesced along r and no column part is
+//      written).
 // Up to LDLT_GROUP panels share one trailing update (K = 64 LDLT_GROUP), a
 // later panel of a group first receiving the group's earlier panels on its own
 // 64 columns.  Against the partial-pivoting LU this halves the trailing flops
@@ -71,16 +73,16 @@ __device__ __forceinline__ bool xcd_item(int wg, int items, int F, int &f, int &
 // kb x kb diagonal block (identity beyond kb).  Step t: every row i > t takes
 // X[i][j] -= (X[i][t] / d_t) X[j][t] for t < j <= i, then column t is scaled
 // by 1/d_t.  Thread tid owns row tid / 4 and the columns j = tid % 4 (mod 4).
-// Afterwards X holds L11 (unit, strictly lower) and D1 (diagonal); D1 and L11
-// go back to the block, D1^-1 and L11^-1 (the LU's right-looking in-place
+// Afterwards X holds L11 (unit, strictly lower) and D1 (diagonal); D1^-1 goes
+// to dinv_g[f N + K0 + t] and L11^-1 (the LU's right-looking in-place
 // inversion) to the scratch, zero-padded beyond kb.
 __global__ void __launch_bounds__(256)
-ldlt_diag_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int K0,
+ldlt_diag_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, int K0,
                  double2 *__restrict__ linv_g, double2 *__restrict__ dinv_g, int *__restrict__ status) {
   __shared__ double2 X[NB][NB + 1];
   __shared__ int zero;
   const int f = blockIdx.x, tid = threadIdx.x;
-  double2 *A = G + (long long)f * gs;
+  const double2 *A = G + (long long)f * gs;
   const int kb = min(NB, N - K0);
   if (tid == 0) zero = 0;
   for (int idx = tid; idx < NB * NB; idx += 256) {
@@ -104,15 +106,10 @@ ldlt_diag_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int K0,
     if (i > t && (t & 3) == j0) X[i][t] = l;
     __syncthreads();
   }
-  // D1^-1 and the factored block
-  if (tid < NB) {
+  // D1^-1
+  if (tid < kb) {
     const double2 d = X[tid][tid];
-    dinv_g[(long long)f * NB + tid] =
-        (tid < kb && !(d.x == 0.0 && d.y == 0.0)) ? zinv(d) : make_double2(0.0, 0.0);
-  }
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx / NB, c = idx - r * NB;
-    if (r < kb && c <= r) A[(long long)(K0 + r) * ldg + K0 + c] = X[r][c];
+    dinv_g[(long long)f * N + K0 + tid] = !(d.x == 0.0 && d.y == 0.0) ? zinv(d) : make_double2(0.0, 0.0);
   }
   __syncthreads();
   if (tid < NB) X[tid][tid] = make_double2(1.0, 0.0);
@@ -139,14 +136,13 @@ ldlt_diag_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int K0,
 // T: one workgroup (4 waves) per (matrix, 64-row block of rows r0.. below the
 // panel).  The A21 block is staged through LDS (coalesced rows); each wave
 // forms 16 rows of W = A21 L11^-T on MFMA (L11^-1 from L2, shared by the
-// matrix's workgroups on its XCD); W goes back to LDS and is stored twice,
-// both times along contiguous rows: the column part L21 = W D1^-1
-// (A[r][K0 + k]) and the row part W^T (A[K0 + k][r]).  Columns >= kb of the
-// block are zero in LDS, rows >= n are not stored.  MFMA layouts:
-// A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16].
+// matrix's workgroups on its XCD); W goes back to LDS and is stored
+// transposed into the row part, A[K0 + k][r] = W[r][k], along contiguous
+// rows.  Columns >= kb of the block are zero in LDS, rows >= n are not
+// stored.  MFMA layouts: A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16].
 __global__ void __launch_bounds__(256)
 ldlt_trsm_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int K0, int F,
-                 int nblk, const double2 *__restrict__ linv_g, const double2 *__restrict__ dinv_g) {
+                 int nblk, const double2 *__restrict__ linv_g) {
   __shared__ double2 S[NB][NB + 1];
   int f, blk;
   if (!xcd_item(blockIdx.x, nblk, F, f, blk)) return;
@@ -189,11 +185,6 @@ ldlt_trsm_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, i
 #pragma unroll
     for (int r = 0; r < 4; ++r) S[wr + 4 * r + lk][16 * b + li] = make_double2(re[b][r], im[b][r]);
   __syncthreads();
-  const double2 *Di = dinv_g + (long long)f * NB;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx / NB, k = idx - r * NB;
-    if (r0 + r < n && k < kb) A[(long long)(r0 + r) * ldg + K0 + k] = zmul(S[r][k], Di[k]);
-  }
   for (int idx = tid; idx < NB * NB; idx += 256) {
     const int k = idx / NB, r = idx - k * NB;
     if (k < kb && r0 + r < n) A[(long long)(K0 + k) * ldg + r0 + r] = S[r][k];
@@ -214,14 +205,19 @@ struct LdltLaunch {
     ldlt_diag_kernel<<<F, 256, 0, s>>>(G, gs, ldg, N, K0, linv, dinv, status);
     const int nblk = (n - K0 - kb + NB - 1) / NB;
     if (nblk > 0)
-      ldlt_trsm_kernel<<<NXCD * fgroups * nblk, 256, 0, s>>>(G, gs, ldg, N, R, K0, F, nblk, linv, dinv);
+      ldlt_trsm_kernel<<<NXCD * fgroups * nblk, 256, 0, s>>>(G, gs, ldg, N, R, K0, F, nblk, linv);
+  }
+  // rows [r0, n) x columns [c0, c1) -= L[.., K range] W^T[K range, ..]
+  void trailing(int r0, int c0, int c1, int kstart, int klen, bool lower) const {
+    launch_trailing_update_sym(G, gs, ldg, N, R, F, r0, c0, c1, kstart, klen, lower, dinv, N, s);
   }
 };
 
 }  // namespace
 
-size_t ldlt_scratch_bytes(int F) {
-  return (size_t)F * (NB * NB + NB) * sizeof(double2) + 256;
+// L11^-1 of the current panel per matrix, then every pivot's D^-1 per matrix.
+size_t ldlt_scratch_bytes(int F, int N) {
+  return (size_t)F * ((size_t)NB * NB + (size_t)N) * sizeof(double2) + 256;
 }
 
 hipError_t launch_ldlt_bordered(double2 *G, long long g_stride, int ldg, int N, int R, int F,
@@ -239,15 +235,15 @@ hipError_t launch_ldlt_bordered(double2 *G, long long g_stride, int ldg, int N, 
       const int a = K0, e = K0 + g * NB;
       for (int p = 0; p < g; ++p) {
         const int b = a + p * NB;
-        if (p > 0) launch_trailing_update(G, g_stride, ldg, N, R, F, b, b, b + NB, a, p * NB, false, stream);
+        if (p > 0) L.trailing(b, b, b + NB, a, p * NB, false);
         L.diag_trsm(b);
       }
-      launch_trailing_update(G, g_stride, ldg, N, R, F, e, e, n, a, g * NB, true, stream);
+      L.trailing(e, e, n, a, g * NB, true);
       K0 = e;
     } else {
       const int kend = min(K0 + NB, N);
       L.diag_trsm(K0);
-      launch_trailing_update(G, g_stride, ldg, N, R, F, kend, kend, n, K0, kend - K0, true, stream);
+      L.trailing(kend, kend, n, K0, kend - K0, true);
       K0 = kend;
     }
   }

@@ -538,10 +538,14 @@ lu_swap_u12_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int K0
 // LOWER: the grid holds only the tiles on or below the diagonal of a square
 // range (row0 == col0, mt_r == mt_c), tile t -> (ti, tj) with
 // t = ti (ti + 1) / 2 + tj, tj <= ti (the symmetric factorisation's update).
-template <bool LOWER>
+// SYM: the left operand comes from the row part as well, A[r][k] = A[k][r] d_k
+// with d_k = dinv[f dinv_ld + k] (the symmetric factorisation keeps only
+// W^T = D L^T in the rows of its panels: L[r][k] = W^T[k][r] / D[k]).
+template <bool LOWER, bool SYM>
 __global__ void __launch_bounds__(256, 3)
 lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, int F, int row0,
-                   int col0, int col_end, int mt_r, int mt_c, int kstart, int klen) {
+                   int col0, int col_end, int mt_r, int mt_c, int kstart, int klen,
+                   const double2 *__restrict__ dinv, int dinv_ld) {
   int f, tile;
   const int items = LOWER ? mt_r * (mt_r + 1) / 2 : mt_r * mt_c;
   if (!xcd_map(blockIdx.x, items, F, f, tile)) return;
@@ -596,16 +600,24 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
   // that are never stored, so their operands come unmasked from a clamped,
   // in-bounds row or column.
   const double2 *lrow[2], *ucol[2];
+  const double2 *dk = SYM ? dinv + (long long)f * dinv_ld + kstart + lk : nullptr;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
-    lrow[a] = A + (long long)min(ra + wr + 16 * a + li, n - 1) * ldg + kstart + lk;
+    lrow[a] = SYM ? A + (long long)(kstart + lk) * ldg + min(ra + wr + 16 * a + li, n - 1)
+                  : A + (long long)min(ra + wr + 16 * a + li, n - 1) * ldg + kstart + lk;
 #pragma unroll
   for (int b = 0; b < 2; ++b)
     ucol[b] = A + (long long)(kstart + lk) * ldg + min(ca + wc + 16 * b + li, col_end - 1);
   const long long ustep = 4LL * ldg;
   auto load_ops = [&](int kk, double2 (&lv)[2], double2 (&uv)[2]) {
+    if (SYM) {
+      const double2 d = dk[kk];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) lv[a] = lrow[a][kk];
+      for (int a = 0; a < 2; ++a) lv[a] = cmul(lrow[a][(kk >> 2) * ustep], d);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 2; ++a) lv[a] = lrow[a][kk];
+    }
 #pragma unroll
     for (int b = 0; b < 2; ++b) uv[b] = ucol[b][(kk >> 2) * ustep];
   };
@@ -630,7 +642,12 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int row = ra + wr + 16 * a + li;
-      lv[a] = (k < klen && row < n) ? A[(long long)row * ldg + kstart + k] : make_double2(0.0, 0.0);
+      if (SYM)
+        lv[a] = (k < klen && row < n)
+                    ? cmul(A[(long long)(kstart + k) * ldg + row], dinv[(long long)f * dinv_ld + kstart + k])
+                    : make_double2(0.0, 0.0);
+      else
+        lv[a] = (k < klen && row < n) ? A[(long long)row * ldg + kstart + k] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
@@ -733,8 +750,8 @@ struct LuLaunch {
     const int n = N + R;
     const int mt_r = (n - r0 + 63) / 64, mt_c = (c1 - c0 + 63) / 64;
     if (mt_r < 1 || mt_c < 1) return;
-    lu_trailing_kernel<false><<<NXCD * fgroups * mt_r * mt_c, 256, 0, s>>>(G, gs, ldg, N, R, F, r0, c0,
-                                                                            c1, mt_r, mt_c, kstart, klen);
+    lu_trailing_kernel<false, false><<<NXCD * fgroups * mt_r * mt_c, 256, 0, s>>>(
+        G, gs, ldg, N, R, F, r0, c0, c1, mt_r, mt_c, kstart, klen, nullptr, 0);
   }
 };
 
@@ -782,18 +799,19 @@ hipError_t launch_lu_bordered(double2 *G, long long g_stride, int ldg, int N, in
   return hipGetLastError();
 }
 
-void launch_trailing_update(double2 *G, long long gs, int ldg, int N, int R, int F, int r0, int c0,
-                            int c1, int kstart, int klen, bool lower, hipStream_t s) {
+void launch_trailing_update_sym(double2 *G, long long gs, int ldg, int N, int R, int F, int r0,
+                                int c0, int c1, int kstart, int klen, bool lower,
+                                const double2 *dinv, int dinv_ld, hipStream_t s) {
   const int n = N + R;
   const int mt_r = (n - r0 + 63) / 64, mt_c = (c1 - c0 + 63) / 64;
   if (mt_r < 1 || mt_c < 1) return;
   const int fgroups = (F + NXCD - 1) / NXCD;
   if (lower)
-    lu_trailing_kernel<true><<<NXCD * fgroups * (mt_r * (mt_r + 1) / 2), 256, 0, s>>>(
-        G, gs, ldg, N, R, F, r0, c0, c1, mt_r, mt_r, kstart, klen);
+    lu_trailing_kernel<true, true><<<NXCD * fgroups * (mt_r * (mt_r + 1) / 2), 256, 0, s>>>(
+        G, gs, ldg, N, R, F, r0, c0, c1, mt_r, mt_r, kstart, klen, dinv, dinv_ld);
   else
-    lu_trailing_kernel<false><<<NXCD * fgroups * mt_r * mt_c, 256, 0, s>>>(G, gs, ldg, N, R, F, r0, c0,
-                                                                            c1, mt_r, mt_c, kstart, klen);
+    lu_trailing_kernel<false, true><<<NXCD * fgroups * mt_r * mt_c, 256, 0, s>>>(
+        G, gs, ldg, N, R, F, r0, c0, c1, mt_r, mt_c, kstart, klen, dinv, dinv_ld);
 }
 
 void launch_bordered_finish(const double2 *G, long long gs, int ldg, int N, int R, int F,

@@ -8,12 +8,14 @@ has an LDL^T factorisation without pivoting whose first N steps leave the
 Schur complement -B^T (1 - Pi)^-1 B in the border block.  The launches, each
 modelled here by one NumPy function:
 
-* D: the 64 x 64 diagonal block is factored L11 D1 L11^T, L11^-1 formed;
-* T: every row block below it: W = A21 L11^-T, the column part becomes
-  L21 = W D1^-1 and the row part (the upper triangle) W^T = D1 L21^T;
-* G: the lower-triangle tiles of the trailing matrix take A -= L21 (W^T),
-  i.e. A22 - L21 D1 L21^T (off-diagonal border-border tiles skipped: only the
-  diagonal of the Schur complement is read).
+* D: the 64 x 64 diagonal block is factored L11 D1 L11^T, L11^-1 formed and
+  D1^-1 kept per pivot;
+* T: every row block below it: W = A21 L11^-T, stored transposed in the row
+  part (the upper triangle): W^T = D1 L21^T;
+* G: the lower-triangle tiles of the trailing matrix take A -= L21 (W^T) with
+  both operands read from the row part, L21[r][k] = W^T[k][r] D^-1[k]
+  (off-diagonal border-border tiles skipped: only the diagonal of the Schur
+  complement is read).
 
 Groups of up to three panels share one trailing update; a later panel of a
 group first receives the group's earlier panels on its own columns.
@@ -24,9 +26,9 @@ import pytest
 NBO = 64
 
 
-def _diag(A, N, K0):
-    """L11 D1 L11^T of the diagonal block (lower triangle read); returns
-    (L11^-1, D1^-1, zero pivot seen)."""
+def _diag(A, N, K0, dinv):
+    """L11 D1 L11^T of the diagonal block (lower triangle read); D1^-1 goes to
+    dinv[K0..]; returns (L11^-1, zero pivot seen)."""
     kb = min(NBO, N - K0)
     X = np.tril(A[K0:K0 + kb, K0:K0 + kb]).astype(complex)
     zero = False
@@ -40,20 +42,24 @@ def _diag(A, N, K0):
         X[t + 1:, t] = col / d
     L = np.tril(X, -1) + np.eye(kb)
     D = np.diag(X).copy()
-    A[K0:K0 + kb, K0:K0 + kb] = np.tril(X)
     with np.errstate(divide="ignore", invalid="ignore"):
-        return np.linalg.inv(L), np.where(D != 0, 1.0 / D, 0.0), zero
+        dinv[K0:K0 + kb] = np.where(D != 0, 1.0 / D, 0.0)
+    return np.linalg.inv(L), zero
 
 
-def _trsm(A, N, K0, Linv, Dinv):
+def _trsm(A, N, K0, Linv):
+    """Row part of the panel: W^T with W = A21 L11^-T (rows below the panel)."""
     kb = min(NBO, N - K0)
     r0 = K0 + kb
-    W = A[r0:, K0:K0 + kb] @ Linv.T
-    A[r0:, K0:K0 + kb] = W * Dinv[None, :]
-    A[K0:K0 + kb, r0:] = W.T
+    A[K0:K0 + kb, r0:] = (A[r0:, K0:K0 + kb] @ Linv.T).T
 
 
-def _tiles_lower(A, N, r0, ks, kl):
+def _lower_operand(A, dinv, rows, ks, kl):
+    """L21 rows `rows` over the K range, from the row part: W^T[k][r] D^-1[k]."""
+    return (A[ks:ks + kl, rows] * dinv[ks:ks + kl, None]).T
+
+
+def _tiles_lower(A, N, r0, ks, kl, dinv):
     n = A.shape[0]
     mt = (n - r0 + 63) // 64
     for ti in range(mt):
@@ -61,15 +67,18 @@ def _tiles_lower(A, N, r0, ks, kl):
             ra, ca = r0 + 64 * ti, r0 + 64 * tj
             if ra >= N and ca >= N and ca + 64 <= ra:
                 continue
-            A[ra:ra + 64, ca:ca + 64] -= A[ra:ra + 64, ks:ks + kl] @ A[ks:ks + kl, ca:ca + 64]
+            rows = slice(ra, min(ra + 64, n))
+            A[rows, ca:ca + 64] -= _lower_operand(A, dinv, rows, ks, kl) @ A[ks:ks + kl, ca:ca + 64]
 
 
-def _columns(A, r0, c0, c1, ks, kl):
-    A[r0:, c0:c1] -= A[r0:, ks:ks + kl] @ A[ks:ks + kl, c0:c1]
+def _columns(A, r0, c0, c1, ks, kl, dinv):
+    rows = slice(r0, A.shape[0])
+    A[rows, c0:c1] -= _lower_operand(A, dinv, rows, ks, kl) @ A[ks:ks + kl, c0:c1]
 
 
 def bordered_ldlt(A, N, group):
     n = A.shape[0]
+    dinv = np.zeros(N, complex)
     K0 = 0
     zero = False
     while K0 < N:
@@ -79,18 +88,18 @@ def bordered_ldlt(A, N, group):
             for p in range(g):
                 b = a + p * NBO
                 if p > 0:
-                    _columns(A, b, b, b + NBO, a, p * NBO)
-                Linv, Dinv, z = _diag(A, N, b)
+                    _columns(A, b, b, b + NBO, a, p * NBO, dinv)
+                Linv, z = _diag(A, N, b, dinv)
                 zero |= z
-                _trsm(A, N, b, Linv, Dinv)
-            _tiles_lower(A, N, e, a, g * NBO)
+                _trsm(A, N, b, Linv)
+            _tiles_lower(A, N, e, a, g * NBO, dinv)
             K0 = e
         else:
             kend = min(K0 + NBO, N)
-            Linv, Dinv, z = _diag(A, N, K0)
+            Linv, z = _diag(A, N, K0, dinv)
             zero |= z
-            _trsm(A, N, K0, Linv, Dinv)
-            _tiles_lower(A, N, kend, K0, kend - K0)
+            _trsm(A, N, K0, Linv)
+            _tiles_lower(A, N, kend, K0, kend - K0, dinv)
             K0 = kend
     return np.diag(A[N:, N:]).copy(), zero
 
