@@ -395,12 +395,16 @@ def serve_main(args):
     th = threading.Thread(target=feeder)
     t_start = time.perf_counter()
     th.start()
-    th.join()
+    # results are collected in arrival order while the feeder still submits
     out = []
-    for k, t in enumerate(tickets):
-        out.append(srv.wait(t))
+    for k in range(len(tickets)):
+        while tickets[k] is None:
+            time.sleep(0.005)
+        out.append(srv.wait(tickets[k]))
         if (k + 1) % 20 == 0:
-            print(f"serve: {k + 1}/{len(tickets)} requests done", file=sys.stderr, flush=True)
+            print(f"serve: {k + 1}/{len(tickets)} requests done "
+                  f"({time.perf_counter() - t_start:.0f} s)", file=sys.stderr, flush=True)
+    th.join()
     wall = time.perf_counter() - t_start
     st = srv.stats()
     srv.close()
@@ -432,6 +436,8 @@ def serve_main(args):
                     "achieved_rate": len(out) / (last - first),
                     "wall_s": wall, "peak_concurrent_requests": st["peak_active"],
                     "peak_in_use_gb": st["peak_in_use_bytes"] / 2 ** 30,
+                    "kept_split_operands_gb": st["kept_bytes"] / 2 ** 30,
+                    "refused_requests": st["refused"],
                     "mean_nbasis": float(np.mean(nbs))},
     }
     emit(line, args.jsonl)

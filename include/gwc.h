@@ -392,7 +392,11 @@ int gwc_sigma_core_resident(gwc_system_handle handle, const gwc_sigma_args *args
  * requests that can never fit are refused at submit (GWC_ERR_OUT_OF_MEMORY).
  * batch_bytes (0 = budget / 4) bounds the batched matrices of one launch of a
  * request and is the same for every request, so each result is independent
- * of what runs beside it.  One request = gwc_sigma_core for one core state
+ * of what runs beside it.  A request's footprint includes the split operands
+ * of the mixed-precision forms when its system has none for its precision
+ * yet; the request that builds them leaves them with the system, and they
+ * stay counted against the budget until the server is destroyed (a queued
+ * request that then no longer fits fails with GWC_ERR_OUT_OF_MEMORY).  One request = gwc_sigma_core for one core state
  * (mode, precision as given) followed by gwc_spectral_cumulant of its
  * Im Sigma^dec when n_t > 0, with the output window starting at
  * E_QP + omega_out_min_rel.  Times are seconds since server creation. */
@@ -429,6 +433,8 @@ typedef struct {
   int32_t queued, active, peak_active;
   long long completed;
   double in_use_bytes, peak_in_use_bytes, budget_bytes;
+  double kept_bytes;  /* split operands built by requests, kept with their systems */
+  long long refused;  /* queued requests failed because they no longer fit */
 } gwc_server_stats_t;
 int gwc_server_create(const gwc_server_config *cfg, gwc_server_handle *server);
 int gwc_server_submit(gwc_server_handle server, const gwc_request *request, int64_t *ticket);

@@ -160,6 +160,7 @@ class GwcServerStats(Structure):
         ("queued", c_int32), ("active", c_int32), ("peak_active", c_int32),
         ("completed", ctypes.c_longlong), ("in_use_bytes", c_double),
         ("peak_in_use_bytes", c_double), ("budget_bytes", c_double),
+        ("kept_bytes", c_double), ("refused", ctypes.c_longlong),
     ]
 
 

@@ -355,11 +355,40 @@ ResidentSystem *create_resident(const gwc_system *sys, hipStream_t s) {
 
 void destroy_resident(ResidentSystem *rs) { delete rs; }
 
+// Tiles of the mixed-precision Pi build that touch the upper triangle.
+std::vector<int2> mixed_tiles(int N, int prec) {
+  std::vector<int2> mt;
+  const int tr = mixed_tile_rows(prec);
+  const int nr_t = (N + tr - 1) / tr;
+  const int nc_t = (N + MX_TILE_COLS - 1) / MX_TILE_COLS;
+  for (int i = 0; i < nr_t; ++i)
+    for (int j = 0; j < nc_t; ++j)
+      if ((j + 1) * MX_TILE_COLS > i * tr) mt.push_back(make_int2(i, j));
+  return mt;
+}
+
+// Device bytes of the split operands of one precision (FP32 L, hi and lo
+// parts in 16-bit slots, column scales, tile list), rows padded to 256.
+size_t split_operand_bytes(const ResidentSystem &rs, int prec) {
+  const int rows_pad = (int)round_up(rs.N, MX_TILE_COLS);
+  const size_t elems = (size_t)rows_pad * rs.ldl;
+  return elems * (sizeof(float) + 2 * sizeof(unsigned short)) + 3 * (size_t)rs.ldl * sizeof(float) +
+         mixed_tiles(rs.N, prec).size() * sizeof(int2);
+}
+
+size_t mixed_operand_bytes(ResidentSystem &rs, int prec) {
+  if (prec == GWC_PREC_FP64) return 0;
+  std::lock_guard<std::mutex> lock(rs.mixed_mutex);
+  return rs.mixed[prec].ready ? 0 : split_operand_bytes(rs, prec);
+}
+
 // Split operands of the mixed-precision Pi build, created once per system and
-// precision (rows padded to 256).
-const MixedOperands &mixed_operands(ResidentSystem &rs, int prec, hipStream_t s) {
+// precision (rows padded to 256); *built (when given) receives the bytes this
+// call allocated (0 when they existed).
+const MixedOperands &mixed_operands(ResidentSystem &rs, int prec, hipStream_t s, size_t *built) {
   std::lock_guard<std::mutex> lock(rs.mixed_mutex);
   MixedOperands &m = rs.mixed[prec];
+  if (built) *built = 0;
   if (m.ready) return m;
   const int rows_pad = (int)round_up(rs.N, MX_TILE_COLS);
   const size_t elems = (size_t)rows_pad * rs.ldl;
@@ -371,19 +400,22 @@ const MixedOperands &mixed_operands(ResidentSystem &rs, int prec, hipStream_t s)
   m.acol.alloc(rs.ldl * sizeof(float));
   launch_mixed_prep(prec, rs.d_L.as<double>(), rs.n_aux_pad, rows_pad, rs.ldl, m.Lf.as<float>(),
                     m.Bh.p, m.Bl.p, m.cs.as<float>(), m.ics.as<float>(), m.acol.as<float>(), s);
-  std::vector<int2> mt;
-  const int tr = mixed_tile_rows(prec);
-  const int nr_t = (rs.N + tr - 1) / tr;
-  const int nc_t = (rs.N + MX_TILE_COLS - 1) / MX_TILE_COLS;
-  for (int i = 0; i < nr_t; ++i)
-    for (int j = 0; j < nc_t; ++j)
-      if ((j + 1) * MX_TILE_COLS > i * tr) mt.push_back(make_int2(i, j));
+  const std::vector<int2> mt = mixed_tiles(rs.N, prec);
   upload(m.tiles, mt, s);
   m.n_tiles = (int)mt.size();
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipStreamSynchronize(s));
   m.ready = true;
+  if (built)
+    *built = m.Lf.bytes + m.Bh.bytes + m.Bl.bytes + m.cs.bytes + m.ics.bytes + m.acol.bytes + m.tiles.bytes;
   return m;
+}
+
+size_t prepare_mixed_operands(ResidentSystem &rs, int prec, hipStream_t s) {
+  if (prec == GWC_PREC_FP64) return 0;
+  size_t built = 0;
+  (void)mixed_operands(rs, prec, s, &built);
+  return built;
 }
 
 namespace {
@@ -893,7 +925,7 @@ void run_sigma(ResidentSystem &rs, const gwc_sigma_args *args, gwc_sigma_out *ou
   const int nc = args->n_core, ni = args->n_imag, nr = args->n_real;
   const bool full = args->mode == GWC_MODE_FULL;
   const MixedOperands *mx = nullptr;
-  if (args->precision != GWC_PREC_FP64) mx = &mixed_operands(rs, args->precision, s);
+  if (args->precision != GWC_PREC_FP64) mx = &mixed_operands(rs, args->precision, s, nullptr);
 
   DevBuf dcore(s), dwi(s), dwwi(s), dwr(s), dvxc(s);
   const int *d_core = upload(dcore, in.core, s);

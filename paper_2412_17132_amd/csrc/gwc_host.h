@@ -47,6 +47,14 @@ void validate_sigma_args(int n_occ, int n_basis, const gwc_sigma_args *args,
 size_t predict_sigma_bytes(const ResidentSystem &rs, const gwc_sigma_args *args,
                            size_t batch_bytes);
 
+// Split operands of the mixed-precision Pi build (built on a resident
+// system's first request at that precision and kept with the system):
+// bytes they would take if not built yet (0 for FP64 or when built), and
+// building them now, returning the bytes this call allocated (0 if they
+// existed).
+size_t mixed_operand_bytes(ResidentSystem &rs, int prec);
+size_t prepare_mixed_operands(ResidentSystem &rs, int prec, hipStream_t s);
+
 // Cumulant spectral function (all pointers host or device).
 void run_cumulant(const gwc_cumulant_args *a, double *A_out, double *z_out, hipStream_t s);
 size_t predict_cumulant_bytes(int n_real, int n_t, int n_out);

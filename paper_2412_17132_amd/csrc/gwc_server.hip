@@ -42,6 +42,7 @@ struct Request {
   int n_t = 0, n_out = 0;
   double d_omega = 0.0, out_min_rel = 0.0;
   size_t footprint = 0;
+  size_t kept = 0;  // bytes this request built for its system (the split operands)
   // results
   bool done = false;
   bool claimed = false;  // a gwc_server_wait holds this ticket (set under the server lock)
@@ -90,6 +91,9 @@ void execute(gwc_server_s *srv, Request *r, hipStream_t s) {
     a.precision = r->precision;
     r->im_dec.assign(nr, 0.0);
     if (r->mode == GWC_MODE_FULL) r->sigma_c.assign(2 * (size_t)nr, 0.0);
+    // the split operands first, so that the bytes this request leaves behind
+    // are known to the admission
+    r->kept = gwc::prepare_mixed_operands(*r->sys, r->precision, s);
     gwc_sigma_out o{};
     o.sigma_c = r->mode == GWC_MODE_FULL ? r->sigma_c.data() : nullptr;
     o.im_sigma_dec = r->im_dec.data();
@@ -127,8 +131,18 @@ void worker_loop(gwc_server_s *srv, int slot) {
   hipStream_t s = srv->streams[slot];
   for (;;) {
     size_t footprint = 0;
-    Request *r = srv->adm->acquire(footprint);
+    bool refused = false;
+    Request *r = srv->adm->acquire(footprint, nullptr, &refused);
     if (!r) return;
+    if (refused) {
+      std::lock_guard<std::mutex> lock(srv->mu);
+      r->status = GWC_ERR_OUT_OF_MEMORY;
+      r->error = "request footprint no longer fits beside the split operands kept for resident systems";
+      r->t_start = r->t_end = srv->now();
+      r->done = true;
+      srv->cv.notify_all();
+      continue;
+    }
     {
       std::lock_guard<std::mutex> lock(srv->mu);
       r->t_start = srv->now();
@@ -139,7 +153,7 @@ void worker_loop(gwc_server_s *srv, int slot) {
       r->t_end = srv->now();
       r->done = true;
     }
-    srv->adm->release(footprint);
+    srv->adm->release(footprint, r->kept);
     srv->cv.notify_all();
   }
 }
@@ -224,10 +238,16 @@ int gwc_server_submit(gwc_server_handle srv, const gwc_request *rq, int64_t *tic
     a.n_imag = rq->n_imag;
     a.n_real = rq->n_real;
     a.mode = rq->mode;
+    a.precision = rq->precision;
+    // transient device memory, plus the split operands when this request may
+    // be the one that builds them (they then stay with the system)
     r->footprint = gwc::predict_sigma_bytes(*sys, &a, srv->batch_bytes) +
-                   (rq->n_t > 0 ? gwc::predict_cumulant_bytes(rq->n_real, rq->n_t, rq->n_out) : 0);
-    if (r->footprint > srv->budget)
-      gwc::fail(GWC_ERR_OUT_OF_MEMORY, "request footprint %zu bytes exceeds the budget %zu", r->footprint, srv->budget);
+                   (rq->n_t > 0 ? gwc::predict_cumulant_bytes(rq->n_real, rq->n_t, rq->n_out) : 0) +
+                   gwc::mixed_operand_bytes(*sys, rq->precision);
+    const size_t room = srv->budget - srv->adm->stats().kept;
+    if (r->footprint > room)
+      gwc::fail(GWC_ERR_OUT_OF_MEMORY, "request footprint %zu bytes exceeds the budget left, %zu of %zu",
+                r->footprint, room, srv->budget);
     {
       // table entry and queue position under one lock: tickets follow queue order
       std::lock_guard<std::mutex> lock(srv->mu);
@@ -236,7 +256,11 @@ int gwc_server_submit(gwc_server_handle srv, const gwc_request *rq, int64_t *tic
       *ticket = r->id;
       Request *rp = r.get();
       srv->reqs.emplace(rp->id, std::move(r));
-      (void)srv->adm->submit(rp, rp->footprint);  // fits: checked above
+      if (!srv->adm->submit(rp, rp->footprint)) {  // kept bytes grew since the check above
+        const size_t fp = rp->footprint;
+        srv->reqs.erase(rp->id);
+        gwc::fail(GWC_ERR_OUT_OF_MEMORY, "request footprint %zu bytes exceeds the budget left", fp);
+      }
     }
     return GWC_OK;
   });
@@ -292,6 +316,8 @@ int gwc_server_stats(gwc_server_handle srv, gwc_server_stats_t *st) {
     st->in_use_bytes = (double)a.in_use;
     st->peak_in_use_bytes = (double)a.peak_in_use;
     st->budget_bytes = (double)srv->budget;
+    st->kept_bytes = (double)a.kept;
+    st->refused = a.refused;
     return GWC_OK;
   });
 }

@@ -177,12 +177,41 @@ void stop_releases_idle_workers() {
 
 }  // namespace
 
+// Kept bytes: a finished request that keeps part of its footprint (device
+// memory it built for a resident system) shrinks the budget for the rest; a
+// queued request that can then never fit is handed out as refused instead of
+// blocking the ones behind it, and a new one is refused at submission.
+void kept_bytes() {
+  gwc::Admission<Item> adm(100);
+  Item a, b, c, d;
+  CHECK(adm.submit(&a, 60));
+  size_t fp = 0;
+  bool refused = true;
+  Item *it = adm.acquire(fp, nullptr, &refused);
+  CHECK(it == &a && !refused && fp == 60);
+  CHECK(adm.submit(&b, 60));  // fits beside nothing kept so far
+  CHECK(adm.submit(&c, 40));
+  adm.release(60, 50);  // a keeps 50 of its 60
+  CHECK(adm.stats().kept == 50 && adm.stats().in_use == 50 && adm.stats().active == 0);
+  it = adm.acquire(fp, nullptr, &refused);  // b: 60 > 100 - 50, refused
+  CHECK(it == &b && refused && fp == 60);
+  it = adm.acquire(fp, nullptr, &refused);  // c: 50 + 40 <= 100
+  CHECK(it == &c && !refused && fp == 40);
+  CHECK(!adm.submit(&d, 70));  // 70 > 100 - 50: refused at submission
+  adm.release(40);
+  const auto st = adm.stats();
+  CHECK(st.in_use == 50 && st.kept == 50 && st.refused == 1 && st.completed == 3);
+  adm.stop();
+  CHECK(adm.acquire(fp) == nullptr);
+}
+
 int main() {
   fifo_single_worker();
   budget_invariant_many_workers();
   oversize_refused();
   head_of_line();
   stop_releases_idle_workers();
+  kept_bytes();
   std::printf("admission: all checks passed\n");
   return 0;
 }

@@ -151,3 +151,36 @@ def test_admission_by_footprint():
     tiny.close()
     for r in res:
         r.close()
+
+
+def test_split_operands_are_charged_and_kept():
+    """The first BF16X3 request on a resident system builds the split operands
+    of the mixed-precision Pi build: its footprint includes them, they stay
+    with the system and stay counted against the budget (kept_bytes), a later
+    request of the same precision is charged only its transient memory, and
+    the device memory the first request took (hipMemGetInfo) lies between the
+    kept bytes and its predicted footprint."""
+    s = system_from_config(serving_request_config(150, 1004))
+    rs = ResidentSystem.from_system(s)
+    srv = Server(n_slots=1, hbm_budget_bytes=8 << 30)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    first = srv.wait(_submit(srv, rs, s, 0, precision="bf16x3"))
+    free1, _ = torch.cuda.mem_get_info()
+    st1 = srv.stats()
+    second = srv.wait(_submit(srv, rs, s, 0, precision="bf16x3"))
+    st2 = srv.stats()
+    plain = srv.wait(_submit(srv, rs, s, 0, precision="fp64"))
+    st3 = srv.stats()
+    srv.close()
+    rs.close()
+    kept = st1["kept_bytes"]
+    print(f"kept {kept / 2**20:.2f} MiB, footprints {first['footprint_bytes'] / 2**20:.2f} / "
+          f"{second['footprint_bytes'] / 2**20:.2f} MiB, device memory taken {(free0 - free1) / 2**20:.2f} MiB")
+    assert kept > 0
+    assert first["footprint_bytes"] - second["footprint_bytes"] == kept
+    assert second["footprint_bytes"] == plain["footprint_bytes"]
+    assert st2["kept_bytes"] == kept and st3["kept_bytes"] == kept
+    assert st1["in_use_bytes"] == kept and st3["in_use_bytes"] == kept
+    assert kept <= free0 - free1 <= first["footprint_bytes"]
+    assert first["e_qp"] == second["e_qp"]
