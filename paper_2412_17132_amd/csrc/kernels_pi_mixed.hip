@@ -17,7 +17,7 @@
 //           aimed one binade higher -> ~2^-7 relative per product
 //
 // Tile: one 128 x 256 block of Pi per workgroup and frequency for the 16-bit
-// forms (8 waves of 32 x 128, v_mfma_f32_16x16x32_{bf16,f16}; every B chunk
+// forms (8 waves of 16 x 256, v_mfma_f32_16x16x32_{bf16,f16}; every B chunk
 // staged in LDS serves 128 rows), 64 x 256 with 4 waves for FP8 (whose B chunk
 // is half the bytes, so occupancy pays more than reuse); upper-triangle blocks
 // only, the result written as 1 - Pi (FP64) into the bordered matrix with its
@@ -314,17 +314,16 @@ mixed_chi_kernel(const double *__restrict__ chi_re, const double *__restrict__ c
 }
 
 // The 16-bit forms with the K chunks double-buffered in LDS.  One workgroup of
-// 16 waves per 128 x 256 tile and frequency; wave w covers rows 16 (w / 2) and
-// 128 columns from 128 (w % 2): 8 blocks of 16 x 16, Re and Im accumulators.
-// Each K chunk of 32 is fetched straight into LDS (global_load_lds, 16 bytes
-// per lane at wave base + 16 lane: no registers, no padding) while the chunk
-// before it is multiplied; the A rows (FP32 L) and the split B rows (64 bytes
-// per row) are each one load per wave.  The chunk's 64 FP32 chi values (Re,
-// Im) travel through a register of the first wave (loaded with the fetch,
-// stored after the multiply).  The reads of a chunk are conflict-free: 16 rows
-// x 64 (B) or 128 (A) bytes contiguous per wave.  Stage buffers are separate
-// __shared__ objects and the loop is unrolled by two, so each multiply names
-// one buffer and each fetch the other.
+// 8 waves per 128 x 256 tile and frequency; wave w covers rows 16 w and all
+// 256 columns: 16 blocks of 16 x 16, Re and Im accumulators.  Each K chunk of
+// 32 is fetched straight into LDS (buffer_load ... lds, 16 bytes per lane at
+// wave base + 16 lane: no registers, no padding) while the chunk before it is
+// multiplied: per wave two 1 KB pieces each of the A rows (FP32 L) and of the
+// split B rows, and the chunk's 64 FP32 chi values (Re, Im) into the wave's
+// own slot.  The reads of a chunk are conflict-free: 16 rows x 64 (B) or 128
+// (A) bytes contiguous per wave.  Stage buffers are separate __shared__
+// objects and the loop is unrolled by two, so each multiply names one buffer
+// and each fetch the other.
 // Raw buffer resources (base, no stride, size in bytes; the gfx9 format word):
 // the hardware returns zeros past the size instead of faulting.
 constexpr int BUF_FORMAT_WORD = 0x00020000;
@@ -409,13 +408,30 @@ __device__ __forceinline__ void mix_multiply(const float *As, const typename Mix
   }
 }
 
+// Workgroup -> (tile, frequency) so that the workgroups one XCD holds at a
+// time share a tile: workgroups are dispatched round-robin over the 8 XCDs,
+// and each XCD's consecutive workgroups take one tile for `group` consecutive
+// frequencies (group = 32, one per CU of the XCD, or F when smaller).  They
+// then read the same A and B rows chunk by chunk, from the XCD's L2.  Blocks
+// of (tile, frequency group) go to the XCDs in turn, so that each XCD gets a
+// mix of diagonal and full tiles.
+constexpr int MX_NXCD = 8;
+__device__ __forceinline__ bool mx_item(int wg, int n_tiles, int F, int group, int &tile, int &f) {
+  const int x = wg % MX_NXCD, j = wg / MX_NXCD;
+  const int blk = (j / group) * MX_NXCD + x;
+  const int g = blk / n_tiles;
+  tile = blk - g * n_tiles;
+  f = g * group + j % group;
+  return g * group < F && f < F;
+}
+
 template <class T>
 __global__ void __launch_bounds__(512, 1)
 pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__restrict__ Bhi,
                             const typename Mix<T>::E *__restrict__ Blo, int ldl, int n_aux,
                             const float *__restrict__ cf_all, const float *__restrict__ tscale,
-                            const int2 *__restrict__ tiles, double2 *__restrict__ G,
-                            long long g_stride, int ldg) {
+                            const int2 *__restrict__ tiles, int n_tiles, int F, int group,
+                            double2 *__restrict__ G, long long g_stride, int ldg) {
   using E = typename Mix<T>::E;
   static_assert(sizeof(E) == 2, "16-bit forms only");
   // two stages as separate objects (the compiler then needs no wait between a
@@ -427,9 +443,10 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
   // fetches can go to M0
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lq = lane >> 4;
-  const int2 tb = tiles[blockIdx.x];
+  int tile, f;
+  if (!mx_item(blockIdx.x, n_tiles, F, group, tile, f)) return;  // uniform: the whole workgroup
+  const int2 tb = tiles[tile];
   const int P0 = tb.x * 128, Q0 = tb.y * MX_TC;
-  const int f = blockIdx.y;
   const int wr = 16 * wave;
   const float *cf = cf_all + (long long)f * 2 * ldl;
   // column blocks this wave needs: some column >= its first row, and < n_aux;
@@ -542,14 +559,18 @@ void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const voi
   if (fp16) taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, Mix<_Float16>::TARGET, acol, tscale);
   mixed_chi_kernel<<<dim3((ldl + 255) / 256, F), 256, 0, stream>>>(
       chi_re, chi_im, ldl, fp16 ? inv_colscale : nullptr, fp16 ? tscale : nullptr, chi_f32);
+  // (tile, frequency-group) blocks, rounded up to a whole turn of the XCDs
+  const int group = F < 32 ? F : 32;
+  const long long blocks = (long long)n_tiles * ((F + group - 1) / group);
+  const long long wgs = (blocks + MX_NXCD - 1) / MX_NXCD * MX_NXCD * group;
   if (fp16)
-    pi_build_mixed_async_kernel<_Float16><<<grid, 512, 0, stream>>>(
+    pi_build_mixed_async_kernel<_Float16><<<(unsigned)wgs, 512, 0, stream>>>(
         Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
-        n_aux, chi_f32, tscale, tiles, G, g_stride, ldg);
+        n_aux, chi_f32, tscale, tiles, n_tiles, F, group, G, g_stride, ldg);
   else
-    pi_build_mixed_async_kernel<__bf16><<<grid, 512, 0, stream>>>(
+    pi_build_mixed_async_kernel<__bf16><<<(unsigned)wgs, 512, 0, stream>>>(
         Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
-        n_aux, chi_f32, nullptr, tiles, G, g_stride, ldg);
+        n_aux, chi_f32, nullptr, tiles, n_tiles, F, group, G, g_stride, ldg);
 }
 
 }  // namespace gwc
