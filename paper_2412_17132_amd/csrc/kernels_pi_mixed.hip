@@ -101,25 +101,47 @@ template <>
 constexpr int mx_rows<e4m3>() { return 64; }
 
 // Per-call preparation: FP32 copy of L (A source) and the split B operand,
-// all [rows_pad][ldl] with rows beyond n_aux_pad zero.  For FP16 and FP8 each
-// column k carries the scale 2^e_k (max_P |L_Pk| 2^e_k in the form's target
-// binade); A is formed with 2^-e_k.  For BF16 colscale is NULL (no scaling).
+// rows beyond n_aux_pad zero.  For FP16 and FP8 each column k carries the
+// scale 2^e_k (max_P |L_Pk| 2^e_k in the form's target binade); A is formed
+// with 2^-e_k.  For BF16 colscale is NULL (no scaling).
+//
+// FP8 keeps [rows_pad][ldl].  The 16-bit forms store MFMA operand fragments,
+// so that the Pi build fetches each 1 KB piece of a tile with one fully
+// contiguous 16-byte-per-lane load and lands it in LDS in the order its
+// products read it: per 16-row block rb and K chunk c of 32 (nch chunks),
+//   B: 64 lanes x 8 elements, lane li + 16 lq holding row 16 rb + li,
+//      K 32 c + 8 lq .. + 7;
+//   A: two pieces j of 64 lanes x 4 floats, lane li + 16 lq of piece j
+//      holding row 16 rb + li, K 32 c + 8 lq + 4 j .. + 3.
+__device__ __forceinline__ long long mix_frag_b(int r, int k, int nch) {
+  const int rb = r >> 4, li = r & 15, c = k >> 5, kk = k & 31;
+  return (((long long)rb * nch + c) * 64 + li + 16 * (kk >> 3)) * 8 + (kk & 7);
+}
+__device__ __forceinline__ long long mix_frag_a(int r, int k, int nch) {
+  const int rb = r >> 4, li = r & 15, c = k >> 5, kk = k & 31;
+  return ((((long long)rb * nch + c) * 2 + ((kk >> 2) & 1)) * 64 + li + 16 * (kk >> 3)) * 4 + (kk & 3);
+}
+
 template <class T>
 __global__ void mixed_prep_kernel(const double *__restrict__ Lp, int n_aux_pad, int rows_pad,
                                   int ldl, const float *__restrict__ colscale,
                                   float *__restrict__ Lf, typename Mix<T>::E *__restrict__ Bhi,
                                   typename Mix<T>::E *__restrict__ Blo) {
+  constexpr bool FRAG = sizeof(typename Mix<T>::E) == 2;
   const long long total = (long long)rows_pad * ldl;
   const long long valid = (long long)n_aux_pad * ldl;
+  const int nch = ldl / MX_KC;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
-    const int k = (int)(idx % ldl);
+    const int r = (int)(idx / ldl), k = (int)(idx % ldl);
     const double v = idx < valid ? Lp[idx] : 0.0;
-    Lf[idx] = (float)v;
+    const long long ia = FRAG ? mix_frag_a(r, k, nch) : idx;
+    const long long ib = FRAG ? mix_frag_b(r, k, nch) : idx;
+    Lf[ia] = (float)v;
     typename Mix<T>::E h, l;
     Mix<T>::split((float)(colscale ? v * (double)colscale[k] : v), h, l);
-    Bhi[idx] = h;
-    Blo[idx] = l;
+    Bhi[ib] = h;
+    Blo[ib] = l;
   }
 }
 
@@ -313,17 +335,16 @@ mixed_chi_kernel(const double *__restrict__ chi_re, const double *__restrict__ c
   o[MX_KC] = (float)chi_im[(long long)f * ldl + k] * s * g;
 }
 
-// The 16-bit forms with the K chunks double-buffered in LDS.  One workgroup of
-// 8 waves per 128 x 256 tile and frequency; wave w covers rows 16 w and all
-// 256 columns: 16 blocks of 16 x 16, Re and Im accumulators.  Each K chunk of
-// 32 is fetched straight into LDS (buffer_load ... lds, 16 bytes per lane at
-// wave base + 16 lane: no registers, no padding) while the chunk before it is
-// multiplied: per wave two 1 KB pieces each of the A rows (FP32 L) and of the
-// split B rows, and the chunk's 64 FP32 chi values (Re, Im) into the wave's
-// own slot.  The reads of a chunk are conflict-free: 16 rows x 64 (B) or 128
-// (A) bytes contiguous per wave.  Stage buffers are separate __shared__
-// objects and the loop is unrolled by two, so each multiply names one buffer
-// and each fetch the other.
+// The 16-bit forms with the K chunks in a three-stage LDS ring.  One
+// workgroup of 8 waves per 128 x 256 tile and frequency; wave w covers rows
+// 16 w and all 256 columns: 16 blocks of 16 x 16, Re and Im accumulators.
+// Each K chunk of 32 is fetched straight into LDS (buffer_load ... lds, 16
+// bytes per lane at piece base + 16 lane: no registers, no padding) two
+// chunks ahead of its multiply: per wave two 1 KB pieces each of the A rows
+// (FP32 L) and of the split B rows, in operand-fragment order, and the
+// chunk's 64 FP32 chi values (Re, Im).  The stages are separate __shared__
+// objects and the loop is unrolled by three, so each multiply names one stage
+// and each fetch another, and the compiler inserts no waits between them.
 // Raw buffer resources (base, no stride, size in bytes; the gfx9 format word):
 // the hardware returns zeros past the size instead of faulting.
 constexpr int BUF_FORMAT_WORD = 0x00020000;
@@ -338,16 +359,39 @@ __device__ __forceinline__ void mix_fetch(float *As, typename Mix<T>::E *Bh, typ
                                           __amdgpu_buffer_rsrc_t rBh, __amdgpu_buffer_rsrc_t rBl,
                                           __amdgpu_buffer_rsrc_t rC, const int (&voA)[2],
                                           const int (&voB)[2], int kc, int wave, int lane) {
-  // the chunk's chi (64 floats) into this wave's own 1 KB of C (lanes 16 and
-  // up read what follows, or past the end of the buffer zeros: unused)
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(rC, C + 256 * wave, 16, 16 * lane, kc * 8, 0, 0);
+  // The chunk offset goes into the per-lane offset, which the hardware checks
+  // against the buffer's size (a load past it reads zeros), not into the
+  // scalar offset.  The chunk's chi (64 floats) goes into the stage's 1 KB of
+  // C, by every wave (the same bytes, so that each wave's own wait covers
+  // them; lanes 16 and up read what follows, or zeros: unused).
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rC, C, 16, 16 * lane + kc * 8, 0, 0, 0);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int q = 2 * wave + j;
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rA, As + 256 * q, 16, voA[j], kc * 4, 0, 0);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rBh, Bh + 512 * q, 16, voB[j], kc * 2, 0, 0);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rBl, Bl + 512 * q, 16, voB[j], kc * 2, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rA, As + 256 * q, 16, voA[j] + kc * 64, 0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rBh, Bh + 512 * q, 16, voB[j] + kc * 32, 0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rBl, Bl + 512 * q, 16, voB[j] + kc * 32, 0, 0, 0);
   }
+}
+
+// Waits until at most one fetch (its 7 loads) of this wave is in flight:
+// s_waitcnt vmcnt(7), the other counters unconstrained (expcnt 7, lgkmcnt 15).
+constexpr int MX_LOADS_PER_FETCH = 7;
+__device__ __forceinline__ void mix_wait_one_fetch() {
+  static_assert(MX_LOADS_PER_FETCH == 7, "the wait below encodes vmcnt(7)");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | MX_LOADS_PER_FETCH);
+}
+
+// The workgroup barrier of the K loop, without the memory fence that
+// __syncthreads adds: that fence waits for every load of the wave, the
+// fetch still in flight included.  The empty asm statements keep the
+// compiler from moving LDS accesses across the barrier; each wave has
+// already waited for its own part of the chunk (mix_wait_one_fetch), and its
+// LDS reads of the chunk before were consumed by its products.
+__device__ __forceinline__ void mix_barrier() {
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
 }
 
 // x = hi + lo for 8 values at once (vector conversions, round to nearest
@@ -368,15 +412,15 @@ __device__ __forceinline__ void split8(f8v x, us8 &hi, us8 &lo) {
   lo = __builtin_bit_cast(us8, __builtin_convertvector(r, t8));
 }
 
-// One wave's 16 rows against the 16 column blocks of a stage: blocks
-// b0 <= b < b1 only (wave-uniform bounds: blocks wholly below the diagonal or
-// past n_aux produce nothing that is stored, and the two waves of a SIMD
-// share its MFMA pipe, so skipping them shortens the tiles that cross the
-// diagonal).
+// One wave's 16 rows against the 16 column blocks of a stage, in groups of
+// four blocks: a group is skipped when none of its blocks is in [b0, b1)
+// (wave-uniform bounds: blocks wholly below the diagonal or past n_aux produce
+// nothing that is stored, and the two waves of a SIMD share its MFMA pipe, so
+// skipping them shortens the tiles that cross the diagonal).
 template <class T>
 __device__ __forceinline__ void mix_multiply(const float *As, const typename Mix<T>::E *Bh,
-                                             const typename Mix<T>::E *Bl, const float *C, int wr,
-                                             int li, int lq, int b0, int b1, f4 (&accr)[16],
+                                             const typename Mix<T>::E *Bl, const float *C, int wave,
+                                             int lane, int lq, int b0, int b1, f4 (&accr)[16],
                                              f4 (&acci)[16]) {
   using E = typename Mix<T>::E;
   using V = typename Mix<T>::V;
@@ -387,23 +431,41 @@ __device__ __forceinline__ void mix_multiply(const float *As, const typename Mix
     // accesses it cannot tell apart from the fetch into the other stage, and
     // it would then wait for that fetch)
     const f8v cr = ld8(C + 8 * lq), ci = ld8(C + MX_KC + 8 * lq);
-    const f8v lv = ld8(As + (wr + li) * MX_KC + 8 * lq);
+    const float4 l0 = reinterpret_cast<const float4 *>(As + 512 * wave)[lane];
+    const float4 l1 = reinterpret_cast<const float4 *>(As + 512 * wave + 256)[lane];
+    const f8v lv = f8v{l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
     split8<T>(lv * cr, arh, arl);
     split8<T>(lv * ci, aih, ail);
   }
-  const E *bh_p = Bh + li * MX_KC + 8 * lq;
-  const E *bl_p = Bl + li * MX_KC + 8 * lq;
+  const E *bh_p = Bh + 8 * lane;
+  const E *bl_p = Bl + 8 * lane;
+  // groups of four column blocks: one uniform branch per group, and a group's
+  // eight LDS reads are issued together ahead of its 24 products (eight
+  // independent accumulator chains)
 #pragma unroll
-  for (int b = 0; b < 16; ++b) {
-    if (b >= b0 && b < b1) {
-      const V bh = *reinterpret_cast<const V *>(bh_p + 16 * b * MX_KC);
-      const V bl = *reinterpret_cast<const V *>(bl_p + 16 * b * MX_KC);
-      accr[b] = Mix<T>::mfma(arh, bh, accr[b]);
-      accr[b] = Mix<T>::mfma(arh, bl, accr[b]);
-      accr[b] = Mix<T>::mfma(arl, bh, accr[b]);
-      acci[b] = Mix<T>::mfma(aih, bh, acci[b]);
-      acci[b] = Mix<T>::mfma(aih, bl, acci[b]);
-      acci[b] = Mix<T>::mfma(ail, bh, acci[b]);
+  for (int g = 0; g < 4; ++g) {
+    if (4 * g + 3 >= b0 && 4 * g < b1) {
+      V bh[4], bl[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bh[j] = *reinterpret_cast<const V *>(bh_p + 512 * (4 * g + j));
+        bl[j] = *reinterpret_cast<const V *>(bl_p + 512 * (4 * g + j));
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        accr[4 * g + j] = Mix<T>::mfma(arh, bh[j], accr[4 * g + j]);
+        acci[4 * g + j] = Mix<T>::mfma(aih, bh[j], acci[4 * g + j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        accr[4 * g + j] = Mix<T>::mfma(arl, bh[j], accr[4 * g + j]);
+        acci[4 * g + j] = Mix<T>::mfma(ail, bh[j], acci[4 * g + j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        accr[4 * g + j] = Mix<T>::mfma(arh, bl[j], accr[4 * g + j]);
+        acci[4 * g + j] = Mix<T>::mfma(aih, bl[j], acci[4 * g + j]);
+      }
     }
   }
 }
@@ -434,11 +496,14 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
                             double2 *__restrict__ G, long long g_stride, int ldg) {
   using E = typename Mix<T>::E;
   static_assert(sizeof(E) == 2, "16-bit forms only");
-  // two stages as separate objects (the compiler then needs no wait between a
-  // fetch into one and the reads of the other)
-  __shared__ float A0[128 * MX_KC], A1[128 * MX_KC];
-  __shared__ E Bh0[MX_TC * MX_KC], Bh1[MX_TC * MX_KC], Bl0[MX_TC * MX_KC], Bl1[MX_TC * MX_KC];
-  __shared__ __attribute__((aligned(32))) float C0[8 * 256], C1[8 * 256];
+  // three stages as separate objects (the compiler then needs no wait between
+  // a fetch into one and the reads of another)
+  struct Stage {
+    float A[128 * MX_KC];
+    E Bh[MX_TC * MX_KC], Bl[MX_TC * MX_KC];
+    float C[256];
+  };
+  __shared__ Stage S0, S1, S2;
   // the wave index is uniform: in a scalar register, the LDS bases of the
   // fetches can go to M0
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -455,23 +520,27 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
   int b0 = (r_first - Q0 - 15 + 15) / 16;  // ceil((r_first - Q0 - 15) / 16) for r_first >= Q0
   if (r_first - Q0 - 15 <= 0) b0 = 0;
   const int b1 = r_first < n_aux ? min(16, (n_aux - Q0 + 15) / 16) : 0;
-  // this tile's 128 A rows and 256 B rows, as buffer resources; piece q of a
-  // buffer is rows 8q (A) or 16q (B) on, lane l at row + l / 8 (A: 8 lanes of
-  // 16 bytes per 128-byte row) or l / 4 (B: 4 lanes per 64-byte row)
+  // This tile's operands in fragment order (mixed_prep_kernel): A from row
+  // block P0 / 16 on (8 blocks of two 1 KB pieces per chunk), B from row block
+  // Q0 / 16 on (16 blocks of one 1 KB piece per chunk), as buffer resources.
+  // Wave w fetches A block w (its own 16 rows) and B blocks 2 w, 2 w + 1; lane
+  // l of a piece loads its bytes 16 l .. 16 l + 15 and lands at 16 l of the
+  // piece in LDS, where the products' lane l reads them (consecutive lanes,
+  // consecutive bytes: coalesced, and no LDS bank conflicts).
+  const int nch = ldl / MX_KC;
   const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
-      (void *)(Lf + (long long)P0 * ldl), 0, 128 * ldl * 4, BUF_FORMAT_WORD);
+      (void *)(Lf + (long long)(P0 / 16) * nch * 512), 0, 8 * nch * 2048, BUF_FORMAT_WORD);
   const __amdgpu_buffer_rsrc_t rBh = __builtin_amdgcn_make_buffer_rsrc(
-      (void *)(Bhi + (long long)Q0 * ldl), 0, MX_TC * ldl * 2, BUF_FORMAT_WORD);
+      (void *)(Bhi + (long long)(Q0 / 16) * nch * 512), 0, 16 * nch * 1024, BUF_FORMAT_WORD);
   const __amdgpu_buffer_rsrc_t rBl = __builtin_amdgcn_make_buffer_rsrc(
-      (void *)(Blo + (long long)Q0 * ldl), 0, MX_TC * ldl * 2, BUF_FORMAT_WORD);
+      (void *)(Blo + (long long)(Q0 / 16) * nch * 512), 0, 16 * nch * 1024, BUF_FORMAT_WORD);
   const __amdgpu_buffer_rsrc_t rC = __builtin_amdgcn_make_buffer_rsrc((void *)cf, 0, 2 * ldl * 4,
                                                                       BUF_FORMAT_WORD);
   int voA[2], voB[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    const int q = 2 * wave + j;
-    voA[j] = ((8 * q + (lane >> 3)) * ldl + (lane & 7) * 4) * 4;
-    voB[j] = ((16 * q + (lane >> 2)) * ldl + (lane & 3) * 8) * 2;
+    voA[j] = (wave * nch * 2 + j) * 1024 + 16 * lane;
+    voB[j] = (2 * wave + j) * nch * 1024 + 16 * lane;
   }
 
   f4 accr[16], acci[16];
@@ -480,24 +549,35 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
     accr[b] = f4{0.f, 0.f, 0.f, 0.f};
     acci[b] = f4{0.f, 0.f, 0.f, 0.f};
   }
-  const int nch = ldl / MX_KC;
-  mix_fetch<T>(A0, Bh0, Bl0, C0, rA, rBh, rBl, rC, voA, voB, 0, wave, lane);
-  int c = 0;
-  for (; c + 1 < nch; c += 2) {  // chunks c (stage 0) and c + 1 (stage 1)
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's fetch of chunk c has landed
-    __syncthreads();                // every wave's has; stage 1 is free again
-    mix_fetch<T>(A1, Bh1, Bl1, C1, rA, rBh, rBl, rC, voA, voB, (c + 1) * MX_KC, wave, lane);
-    mix_multiply<T>(A0, Bh0, Bl0, C0 + 256 * wave, wr, li, lq, b0, b1, accr, acci);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (c + 2 < nch) mix_fetch<T>(A0, Bh0, Bl0, C0, rA, rBh, rBl, rC, voA, voB, (c + 2) * MX_KC, wave, lane);
-    mix_multiply<T>(A1, Bh1, Bl1, C1 + 256 * wave, wr, li, lq, b0, b1, accr, acci);
+  // Three stages: chunk c is in stage c % 3.  Step c waits for its own fetch
+  // of chunk c (the fetch of chunk c + 1 may still be in flight), meets the
+  // other waves at the barrier (every wave's part of chunk c has landed, and
+  // every wave has multiplied chunk c - 1, so its stage is free), issues the
+  // fetch of chunk c + 2 into that stage and multiplies chunk c.  The fetches
+  // are unconditional (the compiler then tells the stages apart and adds no
+  // waits of its own): the two past the last chunk read the rows' next bytes
+  // or zeros into stages that are not multiplied.
+#define MX_STAGE(S) S.A, S.Bh, S.Bl, S.C, rA, rBh, rBl, rC, voA, voB
+#define MX_MUL(S) mix_multiply<T>(S.A, S.Bh, S.Bl, S.C, wave, lane, lq, b0, b1, accr, acci)
+  mix_fetch<T>(MX_STAGE(S0), 0, wave, lane);
+  mix_fetch<T>(MX_STAGE(S1), MX_KC, wave, lane);
+  for (int c = 0; c < nch; c += 3) {
+    mix_wait_one_fetch();
+    mix_barrier();
+    mix_fetch<T>(MX_STAGE(S2), (c + 2) * MX_KC, wave, lane);
+    MX_MUL(S0);
+    mix_wait_one_fetch();
+    mix_barrier();
+    mix_fetch<T>(MX_STAGE(S0), (c + 3) * MX_KC, wave, lane);
+    if (c + 1 < nch) MX_MUL(S1);
+    mix_wait_one_fetch();
+    mix_barrier();
+    mix_fetch<T>(MX_STAGE(S1), (c + 4) * MX_KC, wave, lane);
+    if (c + 2 < nch) MX_MUL(S2);
   }
-  if (c < nch) {  // an odd last chunk, in stage 0
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    mix_multiply<T>(A0, Bh0, Bl0, C0 + 256 * wave, wr, li, lq, b0, b1, accr, acci);
-  }
+  __builtin_amdgcn_s_waitcnt(0);  // no fetch lands after the workgroup's end
+#undef MX_MUL
+#undef MX_STAGE
 
   // upper triangle (col >= row) written with its mirror, as 1 - Pi
   const double unscale = 1.0 / (double)(tscale ? tscale[f] : 1.0f);
