@@ -38,6 +38,7 @@ struct e4m3 {};
 constexpr int MX_TC = MX_TILE_COLS;  // tile columns
 constexpr int MX_NB = MX_TC / 32;      // 16-column blocks per wave (a wave covers MX_TC / 2)
 constexpr int MX_KC = 32;    // K per LDS stage
+typedef float f8v __attribute__((ext_vector_type(8)));
 
 // 16-bit splits (round to nearest even)
 __device__ __forceinline__ unsigned short to_bits(__bf16 x) { return __builtin_bit_cast(unsigned short, x); }
@@ -354,7 +355,7 @@ constexpr int BUF_FORMAT_WORD = 0x00020000;
 // a loop-invariant per-lane byte offset (voA, voB) and the chunk's offset as
 // the scalar offset.
 template <class T>
-__device__ __forceinline__ void mix_fetch(float *As, typename Mix<T>::E *Bh, typename Mix<T>::E *Bl,
+__device__ __forceinline__ void mix_fetch(f8v &areg, typename Mix<T>::E *Bh, typename Mix<T>::E *Bl,
                                           float *C, __amdgpu_buffer_rsrc_t rA,
                                           __amdgpu_buffer_rsrc_t rBh, __amdgpu_buffer_rsrc_t rBl,
                                           __amdgpu_buffer_rsrc_t rC, const int (&voA)[2],
@@ -368,10 +369,14 @@ __device__ __forceinline__ void mix_fetch(float *As, typename Mix<T>::E *Bh, typ
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int q = 2 * wave + j;
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rA, As + 256 * q, 16, voA[j] + kc * 64, 0, 0, 0);
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rBh, Bh + 512 * q, 16, voB[j] + kc * 32, 0, 0, 0);
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rBl, Bl + 512 * q, 16, voB[j] + kc * 32, 0, 0, 0);
   }
+  // the wave's own A rows straight into registers (its lane's 8 floats)
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const f4v a0 = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[0] + kc * 64, 0, 0));
+  const f4v a1 = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[1] + kc * 64, 0, 0));
+  areg = f8v{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 }
 
 // Waits until at most one fetch (its 7 loads) of this wave is in flight:
@@ -396,7 +401,6 @@ __device__ __forceinline__ void mix_barrier() {
 
 // x = hi + lo for 8 values at once (vector conversions, round to nearest
 // even, packed in pairs by the hardware): the same values as Mix<T>::split.
-typedef float f8v __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ f8v ld8(const float *p) {
   const float4 a = reinterpret_cast<const float4 *>(p)[0];
   const float4 b = reinterpret_cast<const float4 *>(p)[1];
@@ -418,7 +422,7 @@ __device__ __forceinline__ void split8(f8v x, us8 &hi, us8 &lo) {
 // nothing that is stored, and the two waves of a SIMD share its MFMA pipe, so
 // skipping them shortens the tiles that cross the diagonal).
 template <class T>
-__device__ __forceinline__ void mix_multiply(const float *As, const typename Mix<T>::E *Bh,
+__device__ __forceinline__ void mix_multiply(const f8v &lv, const typename Mix<T>::E *Bh,
                                              const typename Mix<T>::E *Bl, const float *C, int wave,
                                              int lane, int lq, int b0, int b1, f4 (&accr)[16],
                                              f4 (&acci)[16]) {
@@ -431,9 +435,6 @@ __device__ __forceinline__ void mix_multiply(const float *As, const typename Mix
     // accesses it cannot tell apart from the fetch into the other stage, and
     // it would then wait for that fetch)
     const f8v cr = ld8(C + 8 * lq), ci = ld8(C + MX_KC + 8 * lq);
-    const float4 l0 = reinterpret_cast<const float4 *>(As + 512 * wave)[lane];
-    const float4 l1 = reinterpret_cast<const float4 *>(As + 512 * wave + 256)[lane];
-    const f8v lv = f8v{l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
     split8<T>(lv * cr, arh, arl);
     split8<T>(lv * ci, aih, ail);
   }
@@ -499,11 +500,11 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
   // three stages as separate objects (the compiler then needs no wait between
   // a fetch into one and the reads of another)
   struct Stage {
-    float A[128 * MX_KC];
     E Bh[MX_TC * MX_KC], Bl[MX_TC * MX_KC];
     float C[256];
   };
   __shared__ Stage S0, S1, S2;
+  f8v R0, R1, R2;  // the A rows of the chunk in each stage (registers)
   // the wave index is uniform: in a scalar register, the LDS bases of the
   // fetches can go to M0
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -557,23 +558,23 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
   // are unconditional (the compiler then tells the stages apart and adds no
   // waits of its own): the two past the last chunk read the rows' next bytes
   // or zeros into stages that are not multiplied.
-#define MX_STAGE(S) S.A, S.Bh, S.Bl, S.C, rA, rBh, rBl, rC, voA, voB
-#define MX_MUL(S) mix_multiply<T>(S.A, S.Bh, S.Bl, S.C, wave, lane, lq, b0, b1, accr, acci)
-  mix_fetch<T>(MX_STAGE(S0), 0, wave, lane);
-  mix_fetch<T>(MX_STAGE(S1), MX_KC, wave, lane);
+#define MX_STAGE(S, R) R, S.Bh, S.Bl, S.C, rA, rBh, rBl, rC, voA, voB
+#define MX_MUL(S, R) mix_multiply<T>(R, S.Bh, S.Bl, S.C, wave, lane, lq, b0, b1, accr, acci)
+  mix_fetch<T>(MX_STAGE(S0, R0), 0, wave, lane);
+  mix_fetch<T>(MX_STAGE(S1, R1), MX_KC, wave, lane);
   for (int c = 0; c < nch; c += 3) {
     mix_wait_one_fetch();
     mix_barrier();
-    mix_fetch<T>(MX_STAGE(S2), (c + 2) * MX_KC, wave, lane);
-    MX_MUL(S0);
+    mix_fetch<T>(MX_STAGE(S2, R2), (c + 2) * MX_KC, wave, lane);
+    MX_MUL(S0, R0);
     mix_wait_one_fetch();
     mix_barrier();
-    mix_fetch<T>(MX_STAGE(S0), (c + 3) * MX_KC, wave, lane);
-    if (c + 1 < nch) MX_MUL(S1);
+    mix_fetch<T>(MX_STAGE(S0, R0), (c + 3) * MX_KC, wave, lane);
+    if (c + 1 < nch) MX_MUL(S1, R1);
     mix_wait_one_fetch();
     mix_barrier();
-    mix_fetch<T>(MX_STAGE(S1), (c + 4) * MX_KC, wave, lane);
-    if (c + 2 < nch) MX_MUL(S2);
+    mix_fetch<T>(MX_STAGE(S1, R1), (c + 4) * MX_KC, wave, lane);
+    if (c + 2 < nch) MX_MUL(S2, R2);
   }
   __builtin_amdgcn_s_waitcnt(0);  // no fetch lands after the workgroup's end
 #undef MX_MUL
