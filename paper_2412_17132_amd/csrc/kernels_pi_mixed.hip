@@ -354,30 +354,41 @@ constexpr int BUF_FORMAT_WORD = 0x00020000;
 // LDS stage, two 1 KB pieces of each buffer per wave: buffer_load ... lds with
 // a loop-invariant per-lane byte offset (voA, voB) and the chunk's offset as
 // the scalar offset.
+// The loads of one K chunk (columns kc .. kc + 32), issued in three parts
+// spread over the products of the chunk before (a burst of all of them at
+// once holds the waves at the memory issue queue while the MFMA pipes idle).
+// The chunk offset goes into the per-lane offset, which the hardware checks
+// against the buffer's size (a load past it reads zeros), not into the scalar
+// offset.
 template <class T>
-__device__ __forceinline__ void mix_fetch(f8v &areg, typename Mix<T>::E *Bh, typename Mix<T>::E *Bl,
-                                          float *C, __amdgpu_buffer_rsrc_t rA,
-                                          __amdgpu_buffer_rsrc_t rBh, __amdgpu_buffer_rsrc_t rBl,
-                                          __amdgpu_buffer_rsrc_t rC, const int (&voA)[2],
-                                          const int (&voB)[2], int kc, int wave, int lane) {
-  // The chunk offset goes into the per-lane offset, which the hardware checks
-  // against the buffer's size (a load past it reads zeros), not into the
-  // scalar offset.  The chunk's chi (64 floats) goes into the stage's 1 KB of
-  // C, by every wave (the same bytes, so that each wave's own wait covers
-  // them; lanes 16 and up read what follows, or zeros: unused).
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(rC, C, 16, 16 * lane + kc * 8, 0, 0, 0);
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
+struct MixFetch {
+  using E = typename Mix<T>::E;
+  __amdgpu_buffer_rsrc_t rA, rBh, rBl, rC;
+  int voA[2], voB[2], wave, lane;
+
+  // part 0: the chunk's chi (64 floats) into the stage's 1 KB of C, by every
+  // wave (the same bytes, so that each wave's own wait covers them; lanes 16
+  // and up read what follows, or zeros: unused), and the wave's own A rows
+  // straight into registers (its lane's 8 floats)
+  __device__ __forceinline__ void part0(f8v &areg, float *C, int kc) const {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rC, C, 16, 16 * lane + kc * 8, 0, 0, 0);
+    const f4v a0 = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[0] + kc * 64, 0, 0));
+    const f4v a1 = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[1] + kc * 64, 0, 0));
+    areg = f8v{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+  }
+  // parts 1 and 2: the wave's B pieces 2 wave + j (hi and lo) into the stage
+  __device__ __forceinline__ void partB(int j, E *Bh, E *Bl, int kc) const {
     const int q = 2 * wave + j;
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rBh, Bh + 512 * q, 16, voB[j] + kc * 32, 0, 0, 0);
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rBl, Bl + 512 * q, 16, voB[j] + kc * 32, 0, 0, 0);
   }
-  // the wave's own A rows straight into registers (its lane's 8 floats)
-  typedef float f4v __attribute__((ext_vector_type(4)));
-  const f4v a0 = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[0] + kc * 64, 0, 0));
-  const f4v a1 = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[1] + kc * 64, 0, 0));
-  areg = f8v{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-}
+  __device__ __forceinline__ void all(f8v &areg, E *Bh, E *Bl, float *C, int kc) const {
+    part0(areg, C, kc);
+    partB(0, Bh, Bl, kc);
+    partB(1, Bh, Bl, kc);
+  }
+};
 
 // Waits until at most one fetch (its 7 loads) of this wave is in flight:
 // s_waitcnt vmcnt(7), the other counters unconstrained (expcnt 7, lgkmcnt 15).
@@ -423,12 +434,14 @@ __device__ __forceinline__ void split8(f8v x, us8 &hi, us8 &lo) {
 // skipping them shortens the tiles that cross the diagonal).
 template <class T>
 __device__ __forceinline__ void mix_multiply(const f8v &lv, const typename Mix<T>::E *Bh,
-                                             const typename Mix<T>::E *Bl, const float *C, int wave,
-                                             int lane, int lq, int b0, int b1, f4 (&accr)[16],
-                                             f4 (&acci)[16]) {
+                                             const typename Mix<T>::E *Bl, const float *C, int lane,
+                                             int lq, int b0, int b1, f4 (&accr)[16], f4 (&acci)[16],
+                                             const MixFetch<T> &fetch, f8v &areg_next,
+                                             typename Mix<T>::E *Bh_next, typename Mix<T>::E *Bl_next,
+                                             float *C_next, int kc_next) {
   using E = typename Mix<T>::E;
   using V = typename Mix<T>::V;
-  if (b0 >= b1) return;
+  fetch.part0(areg_next, C_next, kc_next);
   V arh, arl, aih, ail;
   {
     // 16-byte LDS reads only (a 32-byte read is split by the compiler into
@@ -445,6 +458,7 @@ __device__ __forceinline__ void mix_multiply(const f8v &lv, const typename Mix<T
   // independent accumulator chains)
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
+    if (g == 1 || g == 2) fetch.partB(g - 1, Bh_next, Bl_next, kc_next);
     if (4 * g + 3 >= b0 && 4 * g < b1) {
       V bh[4], bl[4];
 #pragma unroll
@@ -537,11 +551,17 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
       (void *)(Blo + (long long)(Q0 / 16) * nch * 512), 0, 16 * nch * 1024, BUF_FORMAT_WORD);
   const __amdgpu_buffer_rsrc_t rC = __builtin_amdgcn_make_buffer_rsrc((void *)cf, 0, 2 * ldl * 4,
                                                                       BUF_FORMAT_WORD);
-  int voA[2], voB[2];
+  MixFetch<T> fetch;
+  fetch.rA = rA;
+  fetch.rBh = rBh;
+  fetch.rBl = rBl;
+  fetch.rC = rC;
+  fetch.wave = wave;
+  fetch.lane = lane;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    voA[j] = (wave * nch * 2 + j) * 1024 + 16 * lane;
-    voB[j] = (2 * wave + j) * nch * 1024 + 16 * lane;
+    fetch.voA[j] = (wave * nch * 2 + j) * 1024 + 16 * lane;
+    fetch.voB[j] = (2 * wave + j) * nch * 1024 + 16 * lane;
   }
 
   f4 accr[16], acci[16];
@@ -553,32 +573,32 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
   // Three stages: chunk c is in stage c % 3.  Step c waits for its own fetch
   // of chunk c (the fetch of chunk c + 1 may still be in flight), meets the
   // other waves at the barrier (every wave's part of chunk c has landed, and
-  // every wave has multiplied chunk c - 1, so its stage is free), issues the
-  // fetch of chunk c + 2 into that stage and multiplies chunk c.  The fetches
-  // are unconditional (the compiler then tells the stages apart and adds no
-  // waits of its own): the two past the last chunk read the rows' next bytes
-  // or zeros into stages that are not multiplied.
-#define MX_STAGE(S, R) R, S.Bh, S.Bl, S.C, rA, rBh, rBl, rC, voA, voB
-#define MX_MUL(S, R) mix_multiply<T>(R, S.Bh, S.Bl, S.C, wave, lane, lq, b0, b1, accr, acci)
-  mix_fetch<T>(MX_STAGE(S0, R0), 0, wave, lane);
-  mix_fetch<T>(MX_STAGE(S1, R1), MX_KC, wave, lane);
+  // every wave has multiplied chunk c - 1, so its stage is free) and
+  // multiplies chunk c, issuing the fetch of chunk c + 2 into that stage
+  // between its column groups.  Every step fetches (the compiler then tells
+  // the stages apart and adds no waits of its own): the two fetches past the
+  // last chunk read the rows' next bytes or zeros into stages that are not
+  // multiplied.
+#define MX_MUL(S, R, N, RN, kn, bend) \
+  mix_multiply<T>(R, S.Bh, S.Bl, S.C, lane, lq, b0, bend, accr, acci, fetch, RN, N.Bh, N.Bl, N.C, kn)
+  fetch.all(R0, S0.Bh, S0.Bl, S0.C, 0);
+  fetch.all(R1, S1.Bh, S1.Bl, S1.C, MX_KC);
   for (int c = 0; c < nch; c += 3) {
+    // a step past the last chunk multiplies nothing (no column block below
+    // 0) but still fetches, so that the loads in flight stay what the waits
+    // count and no fetch sits in a branch
     mix_wait_one_fetch();
     mix_barrier();
-    mix_fetch<T>(MX_STAGE(S2, R2), (c + 2) * MX_KC, wave, lane);
-    MX_MUL(S0, R0);
+    MX_MUL(S0, R0, S2, R2, (c + 2) * MX_KC, b1);
     mix_wait_one_fetch();
     mix_barrier();
-    mix_fetch<T>(MX_STAGE(S0, R0), (c + 3) * MX_KC, wave, lane);
-    if (c + 1 < nch) MX_MUL(S1, R1);
+    MX_MUL(S1, R1, S0, R0, (c + 3) * MX_KC, c + 1 < nch ? b1 : 0);
     mix_wait_one_fetch();
     mix_barrier();
-    mix_fetch<T>(MX_STAGE(S1, R1), (c + 4) * MX_KC, wave, lane);
-    if (c + 2 < nch) MX_MUL(S2, R2);
+    MX_MUL(S2, R2, S1, R1, (c + 4) * MX_KC, c + 2 < nch ? b1 : 0);
   }
   __builtin_amdgcn_s_waitcnt(0);  // no fetch lands after the workgroup's end
 #undef MX_MUL
-#undef MX_STAGE
 
   // upper triangle (col >= row) written with its mirror, as 1 - Pi
   const double unscale = 1.0 / (double)(tscale ? tscale[f] : 1.0f);
