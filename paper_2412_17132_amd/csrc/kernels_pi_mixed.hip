@@ -426,6 +426,23 @@ __device__ __forceinline__ void split8(f8v x, us8 &hi, us8 &lo) {
   hi = __builtin_bit_cast(us8, h);
   lo = __builtin_bit_cast(us8, __builtin_convertvector(r, t8));
 }
+// bf16: hi back in FP32 straight from its packed bits (a bf16 is the top half
+// of an FP32), instead of converting each value again
+template <>
+__device__ __forceinline__ void split8<__bf16>(f8v x, us8 &hi, us8 &lo) {
+  typedef __bf16 t8 __attribute__((ext_vector_type(8)));
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  const t8 h = __builtin_convertvector(x, t8);
+  const u4 p = __builtin_bit_cast(u4, h);  // element 2 i in the low half of word i
+  const u4 e = p << 16, o = p & 0xFFFF0000u;
+  // (subscripts: .y/.z/.w inside __builtin_bit_cast were seen to read lane 0)
+  const f8v hf = f8v{__builtin_bit_cast(float, (unsigned)e[0]), __builtin_bit_cast(float, (unsigned)o[0]),
+                     __builtin_bit_cast(float, (unsigned)e[1]), __builtin_bit_cast(float, (unsigned)o[1]),
+                     __builtin_bit_cast(float, (unsigned)e[2]), __builtin_bit_cast(float, (unsigned)o[2]),
+                     __builtin_bit_cast(float, (unsigned)e[3]), __builtin_bit_cast(float, (unsigned)o[3])};
+  hi = __builtin_bit_cast(us8, h);
+  lo = __builtin_bit_cast(us8, __builtin_convertvector(x - hf, t8));
+}
 
 // One wave's 16 rows against the 16 column blocks of a stage, in groups of
 // four blocks: a group is skipped when none of its blocks is in [b0, b1)
