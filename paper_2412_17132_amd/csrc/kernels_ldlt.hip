@@ -168,15 +168,18 @@ ldlt_trsm_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, i
   for (int kk = 0; kk < kb; kk += 4) {
     const int k = kk + lk;
     // A operand: rows wr + li of the block, column k; B operand:
-    // L11^-T [k][c] = L11^-1 [c][k] (zero for k >= kb), c = 16 b + li
+    // L11^-T [k][c] = L11^-1 [c][k] (zero for k >= kb), c = 16 b + li.
+    // Column block b needs k <= 16 b + 15 only: L11^-1 is lower triangular.
     const double2 av = S[wr + li][k];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const double2 bv = Li[(16 * b + li) * NB + k];
-      re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, re[b], 0, 0, 0);
-      re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, re[b], 0, 0, 0);
-      im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, im[b], 0, 0, 0);
-      im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, im[b], 0, 0, 0);
+      if (kk < 16 * b + 16) {
+        const double2 bv = Li[(16 * b + li) * NB + k];
+        re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, re[b], 0, 0, 0);
+        re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, re[b], 0, 0, 0);
+        im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, im[b], 0, 0, 0);
+        im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, im[b], 0, 0, 0);
+      }
     }
   }
   __syncthreads();  // every wave has read its A21 rows
