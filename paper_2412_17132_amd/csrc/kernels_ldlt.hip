@@ -43,7 +43,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int NB = 64;
 constexpr int NXCD = 8;
-constexpr int LDLT_GROUP = 3;
+constexpr int LDLT_GROUP = 4;
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);

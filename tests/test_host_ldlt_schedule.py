@@ -17,7 +17,7 @@ modelled here by one NumPy function:
   (off-diagonal border-border tiles skipped: only the diagonal of the Schur
   complement is read).
 
-Groups of up to three panels share one trailing update; a later panel of a
+Groups of up to four panels share one trailing update; a later panel of a
 group first receives the group's earlier panels on its own columns.
 """
 import numpy as np
@@ -118,7 +118,7 @@ def _stale_upper(A, rng):
     return A
 
 
-@pytest.mark.parametrize("group", [1, 2, 3])
+@pytest.mark.parametrize("group", [1, 2, 3, 4])
 @pytest.mark.parametrize("N,R", [(300, 3), (129, 1), (200, 40), (64, 2), (191, 5), (1200, 1)])
 def test_schedule_gives_the_schur_complement(group, N, R):
     """Complex symmetric with positive definite imaginary part (a residue
@@ -143,7 +143,7 @@ def test_groups_do_not_change_the_result():
     G = rng.normal(size=(N, N)) / np.sqrt(N)
     M = np.eye(N) + 2.0 * (X + X.T) + 1j * 0.1 * (G @ G.T)
     B = rng.normal(size=(N, R))
-    out = [bordered_ldlt(_bordered(M, B), N, g)[0] for g in (1, 2, 3)]
+    out = [bordered_ldlt(_bordered(M, B), N, g)[0] for g in (1, 2, 3, 4)]
     for s in out[1:]:
         assert np.max(np.abs(s - out[0])) <= 1e-12 * np.max(np.abs(out[0]))
 
