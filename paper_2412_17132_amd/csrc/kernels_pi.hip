@@ -103,6 +103,10 @@ pi_build_f64_kernel(const double *__restrict__ Lp, int ldl, int n_aux,
   const int f0 = blockIdx.y * FB;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
+  // on a diagonal tile the lower-left quadrant is the mirror of the upper-right
+  // one: its wave stages operands with the others but forms no products, and
+  // the upper-right wave writes both
+  const bool idle = tb.x == tb.y && wr > wc;
 
   d4 acc[FB][2][2][2];
 #pragma unroll
@@ -146,6 +150,7 @@ pi_build_f64_kernel(const double *__restrict__ Lp, int ldl, int n_aux,
 
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
+      if (idle) continue;  // uniform: the whole wave
       const int k = kk + lk;
       const double a0 = As[(wr + li) * LDA + k];
       const double a1 = As[(wr + 16 + li) * LDA + k];
@@ -168,8 +173,10 @@ pi_build_f64_kernel(const double *__restrict__ Lp, int ldl, int n_aux,
     __syncthreads();
   }
 
-  // store 1 - Pi (and its mirror for off-diagonal tiles)
-  const bool mirror = tb.x != tb.y;
+  // store 1 - Pi (and its mirror for off-diagonal tiles and the upper-right
+  // quadrant of a diagonal tile)
+  if (idle) return;
+  const bool mirror = tb.x != tb.y || wr < wc;
 #pragma unroll
   for (int f = 0; f < FB; ++f) {
     const int fg = f0 + f;
