@@ -813,8 +813,10 @@ def main():
                 "core_shift_g0w0_ev": [float(x) for x in (e1[core] - s.eps[core]) * EV_PER_HA],
                 "core_shift_evgw0_ev": [float(x) for x in (eq[core] - s.eps[core]) * EV_PER_HA]}
 
-    def leg_whole(name, mode):
-        """One whole core state (core 0) of a larger workload, unsampled."""
+    def leg_whole(name, mode, mixed=()):
+        """One whole core state (core 0) of a larger workload, unsampled, in FP64
+        and then in each precision form of `mixed` on the same resident system
+        (speed-up and deviation from the FP64 solve)."""
         def run():
             cf = CONFIGS[name]
             tg = time.perf_counter()
@@ -831,17 +833,36 @@ def main():
             p, u = gwc.timing_get("pi_build_f64"), gwc.timing_get(FACT_TIMER)
             gwc.timing_enable(False)
             e_qp = float(out["e_qp"][0])
-            del sd, out, A, z
+            rec = {"workload": f"{cf.name}: {cf.description}; core 0, {mode.upper()}, FP64, whole and "
+                               f"unsampled (no warm-up: first call on this system)",
+                   "value": 1.0 / el, "unit": "solves/s", "s_per_solve": el,
+                   "residue_tasks": tasks, "n_imag": cf.n_imag, "n_real": cf.n_real,
+                   "pi_build": {"ms": p["total_ms"], "launches": p["launches"], "tflops": _rate(p),
+                                "frac": _rate(p) / FP64_MFMA_PEAK_TFLOPS},
+                   FACT_TIMER: {"ms": u["total_ms"], "launches": u["launches"], "tflops": _rate(u)},
+                   "e_qp_shift_ev": (e_qp - float(sh.eps[0])) * EV_PER_HA,
+                   "setup_s": t_gen}
+            ref = {0: (out, A, z)}
+            for prec in mixed:
+                gwc.timing_enable(True)
+                tw = time.perf_counter()
+                got = solve(0, prec, mode, None, sh, sd)
+                torch.cuda.synchronize()
+                el_m = time.perf_counter() - tw
+                pm, um = gwc.timing_get("pi_build_mixed"), gwc.timing_get(FACT_TIMER)
+                gwc.timing_enable(False)
+                issued = 3 * _rate(pm)
+                rec.setdefault("mixed", {})[prec] = {
+                    "s_per_solve": el_m, "speedup_vs_fp64": el / el_m,
+                    "pi_build_ms": pm["total_ms"], "pi_build_algorithmic_tflops": _rate(pm),
+                    "pi_build_mfma_frac": issued / MIXED_MFMA_PEAK_TFLOPS[prec],
+                    "factorization_ms": um["total_ms"],
+                    "vs_fp64": _compare_solves(ref, {0: got}, sh.eta, n_out, d_omega),
+                    "note": "first call in this precision on the system (includes building its split operands)"}
+                del got
+            del sd, out, A, z, ref
             torch.cuda.empty_cache()
-            return {"workload": f"{cf.name}: {cf.description}; core 0, {mode.upper()}, FP64, whole and "
-                                f"unsampled (no warm-up: first call on this system)",
-                    "value": 1.0 / el, "unit": "solves/s", "s_per_solve": el,
-                    "residue_tasks": tasks, "n_imag": cf.n_imag, "n_real": cf.n_real,
-                    "pi_build": {"ms": p["total_ms"], "launches": p["launches"], "tflops": _rate(p),
-                                 "frac": _rate(p) / FP64_MFMA_PEAK_TFLOPS},
-                    FACT_TIMER: {"ms": u["total_ms"], "launches": u["launches"], "tflops": _rate(u)},
-                    "e_qp_shift_ev": (e_qp - float(sh.eps[0])) * EV_PER_HA,
-                    "setup_s": t_gen}
+            return rec
         return run
 
     def leg_peaks():
@@ -869,9 +890,11 @@ def main():
         elif leg == "decoupled" and args.mode == "full":
             guard.run(res, "decoupled", 0.3 * (n_core + 1) * t_step + 5, leg_decoupled)
         elif leg == "c3" and args.config == "c2":
-            guard.run(res, "c3_full_fp64", scaled("c3", "full"), leg_whole("c3", "full"))
+            guard.run(res, "c3_full_fp64", 1.6 * scaled("c3", "full"),
+                      leg_whole("c3", "full", ("bf16x3", "fp16x3")))
         elif leg == "c4" and args.config == "c2":
-            guard.run(res, "c4_decoupled_fp64", scaled("c4", "decoupled"), leg_whole("c4", "decoupled"))
+            guard.run(res, "c4_decoupled_fp64", 1.6 * scaled("c4", "decoupled"),
+                      leg_whole("c4", "decoupled", ("bf16x3", "fp8")))
         elif leg == "wac":
             guard.run(res, "wac", 0.6 * (n_core + 1) * t_step + 10, leg_wac)
         elif leg == "analytic" and args.mode == "full":
