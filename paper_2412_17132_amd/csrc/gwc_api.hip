@@ -368,10 +368,11 @@ std::vector<int2> mixed_tiles(int N, int prec) {
 }
 
 // Device bytes of the split operands of one precision (FP32 L, hi and lo
-// parts in 16-bit slots, column scales, tile list), rows padded to 256.
+// parts in 16-bit slots, column scales, tile list), rows padded to 256 and
+// columns to the form's K chunk.
 size_t split_operand_bytes(const ResidentSystem &rs, int prec) {
   const int rows_pad = (int)round_up(rs.N, MX_TILE_COLS);
-  const size_t elems = (size_t)rows_pad * rs.ldl;
+  const size_t elems = (size_t)rows_pad * mixed_ldl(prec, rs.ldl);
   return elems * (sizeof(float) + 2 * sizeof(unsigned short)) + 3 * (size_t)rs.ldl * sizeof(float) +
          mixed_tiles(rs.N, prec).size() * sizeof(int2);
 }
@@ -391,15 +392,17 @@ const MixedOperands &mixed_operands(ResidentSystem &rs, int prec, hipStream_t s,
   if (built) *built = 0;
   if (m.ready) return m;
   const int rows_pad = (int)round_up(rs.N, MX_TILE_COLS);
-  const size_t elems = (size_t)rows_pad * rs.ldl;
+  const int ldlk = mixed_ldl(prec, rs.ldl);
+  const size_t elems = (size_t)rows_pad * ldlk;
   m.Lf.alloc(elems * sizeof(float));
   m.Bh.alloc(elems * sizeof(unsigned short));
   m.Bl.alloc(elems * sizeof(unsigned short));
   m.cs.alloc(rs.ldl * sizeof(float));
   m.ics.alloc(rs.ldl * sizeof(float));
   m.acol.alloc(rs.ldl * sizeof(float));
-  launch_mixed_prep(prec, rs.d_L.as<double>(), rs.n_aux_pad, rows_pad, rs.ldl, m.Lf.as<float>(),
-                    m.Bh.p, m.Bl.p, m.cs.as<float>(), m.ics.as<float>(), m.acol.as<float>(), s);
+  launch_mixed_prep(prec, rs.d_L.as<double>(), rs.n_aux_pad, rows_pad, rs.ldl, ldlk,
+                    m.Lf.as<float>(), m.Bh.p, m.Bl.p, m.cs.as<float>(), m.ics.as<float>(),
+                    m.acol.as<float>(), s);
   const std::vector<int2> mt = mixed_tiles(rs.N, prec);
   upload(m.tiles, mt, s);
   m.n_tiles = (int)mt.size();

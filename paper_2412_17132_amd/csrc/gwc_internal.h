@@ -36,15 +36,17 @@ void launch_pi_build_f64(const double *Lp, int ldl, int n_aux, const double *chi
                          const double *chi_im, int F, const int2 *tiles, int n_tiles,
                          double2 *G, long long g_stride, int ldg, hipStream_t stream);
 // Mixed-precision Pi build.  Tiles are mixed_tile_rows(prec) x MX_TILE_COLS
-// blocks (128 x 256 for the 16-bit forms, 64 x 256 for FP8); the split operands
-// have their rows padded to a multiple of MX_TILE_COLS.
+// blocks (128 x 256); the split operands have their rows padded to a multiple
+// of MX_TILE_COLS and their columns to mixed_ldl(prec, ldl) (the form's K
+// chunk: 32 for the 16-bit forms, 64 for FP8).
 constexpr int MX_TILE_COLS = 256;
-constexpr int mixed_tile_rows(int prec) { return prec == 3 ? 64 : 128; }
+constexpr int mixed_tile_rows(int) { return 128; }
+constexpr int mixed_ldl(int prec, int ldl) { return prec == 3 ? (ldl + 63) / 64 * 64 : ldl; }
 // prec 1 BF16X3, 2 FP16X3, 3 FP8X3; Bhi / Blo hold 16-bit (1, 2) or 8-bit (3)
-// elements.
-void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, float *Lf,
-                       void *Bhi, void *Blo, float *colscale, float *inv_colscale, float *acol,
-                       hipStream_t stream);
+// elements, rows_pad x ldlk of them (ldlk = mixed_ldl(prec, ldl)).
+void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, int ldlk,
+                       float *Lf, void *Bhi, void *Blo, float *colscale, float *inv_colscale,
+                       float *acol, hipStream_t stream);
 // chi_f32 is a workspace of F x 2 x ldl floats (the 16-bit forms' scaled FP32 chi).
 void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const void *Blo, int ldl,
                            int n_aux, const double *chi_re, const double *chi_im,

@@ -16,12 +16,10 @@
 //   FP8X3:  fp8 e4m3 (4-bit significand, largest 448) with the same scaling
 //           aimed one binade higher -> ~2^-7 relative per product
 //
-// Tile: one 128 x 256 block of Pi per workgroup and frequency for the 16-bit
-// forms (8 waves of 16 x 256, v_mfma_f32_16x16x32_{bf16,f16}; every B chunk
-// staged in LDS serves 128 rows), 64 x 256 with 4 waves for FP8 (whose B chunk
-// is half the bytes, so occupancy pays more than reuse); upper-triangle blocks
-// only, the result written as 1 - Pi (FP64) into the bordered matrix with its
-// mirror.
+// Tile: one 128 x 256 block of Pi per workgroup and frequency (8 waves of
+// 16 x 256, v_mfma_f32_16x16x32_{bf16,f16,fp8}; every B chunk staged in LDS
+// serves 128 rows); upper-triangle blocks only, the result written as 1 - Pi
+// (FP64) into the bordered matrix with its mirror.
 #include "gwc_internal.h"
 
 namespace gwc {
@@ -36,8 +34,7 @@ typedef unsigned char uc8 __attribute__((ext_vector_type(8)));
 struct e4m3 {};
 
 constexpr int MX_TC = MX_TILE_COLS;  // tile columns
-constexpr int MX_NB = MX_TC / 32;      // 16-column blocks per wave (a wave covers MX_TC / 2)
-constexpr int MX_KC = 32;    // K per LDS stage
+constexpr int MX_KSTEP = 32;  // K of one MFMA step (chi is laid out per step)
 typedef float f8v __attribute__((ext_vector_type(8)));
 
 // 16-bit splits (round to nearest even)
@@ -95,52 +92,62 @@ struct Mix<e4m3> {
 };
 
 // ---------------------------------------------------------------------------
-// Tile rows per form (threads = 4 x rows: one wave per 16 rows).
+// K per chunk of the Pi build: one MFMA K step (32) for the 16-bit forms, two
+// for FP8, so that a lane's 16-byte load holds 8 one-byte values of each step.
 template <class T>
-constexpr int mx_rows() { return 128; }
+struct MixK {
+  static constexpr int KC = 32, STEPS = 1;
+};
 template <>
-constexpr int mx_rows<e4m3>() { return 64; }
+struct MixK<e4m3> {
+  static constexpr int KC = 64, STEPS = 2;
+};
 
 // Per-call preparation: FP32 copy of L (A source) and the split B operand,
-// rows beyond n_aux_pad zero.  For FP16 and FP8 each column k carries the
-// scale 2^e_k (max_P |L_Pk| 2^e_k in the form's target binade); A is formed
-// with 2^-e_k.  For BF16 colscale is NULL (no scaling).
+// rows beyond n_aux_pad and columns beyond ldl zero (the operands span ldlk
+// columns, a multiple of the form's chunk).  For FP16 and FP8 each column k
+// carries the scale 2^e_k (max_P |L_Pk| 2^e_k in the form's target binade);
+// A is formed with 2^-e_k.  For BF16 colscale is NULL (no scaling).
 //
-// FP8 keeps [rows_pad][ldl].  The 16-bit forms store MFMA operand fragments,
-// so that the Pi build fetches each 1 KB piece of a tile with one fully
-// contiguous 16-byte-per-lane load and lands it in LDS in the order its
-// products read it: per 16-row block rb and K chunk c of 32 (nch chunks),
-//   B: 64 lanes x 8 elements, lane li + 16 lq holding row 16 rb + li,
-//      K 32 c + 8 lq .. + 7;
-//   A: two pieces j of 64 lanes x 4 floats, lane li + 16 lq of piece j
-//      holding row 16 rb + li, K 32 c + 8 lq + 4 j .. + 3.
+// Both are stored in MFMA operand-fragment order, so that the Pi build
+// fetches each 1 KB piece of a tile with one fully contiguous 16-byte-per-lane
+// load and finds it in the order its products read it: per 16-row block rb
+// and K chunk c (nch chunks of KC), with step s = (k mod KC) / 32 and
+// q = k mod 32,
+//   B: 64 lanes x 16 bytes; lane li + 16 (q / 8) holds row 16 rb + li, as
+//      element 8 s + q mod 8 of its 16 bytes;
+//   A: 2 STEPS pieces of 64 lanes x 4 floats; lane li + 16 (q / 8) of piece
+//      2 s + (q mod 8) / 4 holds row 16 rb + li, as float q mod 4.
+template <class T>
 __device__ __forceinline__ long long mix_frag_b(int r, int k, int nch) {
-  const int rb = r >> 4, li = r & 15, c = k >> 5, kk = k & 31;
-  return (((long long)rb * nch + c) * 64 + li + 16 * (kk >> 3)) * 8 + (kk & 7);
+  constexpr int KC = MixK<T>::KC, EPL = 16 / (int)sizeof(typename Mix<T>::E);
+  const int rb = r >> 4, li = r & 15, c = k / KC, kk = k % KC, st = kk >> 5, q = kk & 31;
+  return (((long long)rb * nch + c) * 64 + li + 16 * (q >> 3)) * EPL + 8 * st + (q & 7);
 }
+template <class T>
 __device__ __forceinline__ long long mix_frag_a(int r, int k, int nch) {
-  const int rb = r >> 4, li = r & 15, c = k >> 5, kk = k & 31;
-  return ((((long long)rb * nch + c) * 2 + ((kk >> 2) & 1)) * 64 + li + 16 * (kk >> 3)) * 4 + (kk & 3);
+  constexpr int KC = MixK<T>::KC, AP = 2 * MixK<T>::STEPS;
+  const int rb = r >> 4, li = r & 15, c = k / KC, kk = k % KC, st = kk >> 5, q = kk & 31;
+  return ((((long long)rb * nch + c) * AP + 2 * st + ((q >> 2) & 1)) * 64 + li + 16 * (q >> 3)) * 4 +
+         (q & 3);
 }
 
 template <class T>
 __global__ void mixed_prep_kernel(const double *__restrict__ Lp, int n_aux_pad, int rows_pad,
-                                  int ldl, const float *__restrict__ colscale,
+                                  int ldl, int ldlk, const float *__restrict__ colscale,
                                   float *__restrict__ Lf, typename Mix<T>::E *__restrict__ Bhi,
                                   typename Mix<T>::E *__restrict__ Blo) {
-  constexpr bool FRAG = sizeof(typename Mix<T>::E) == 2;
-  const long long total = (long long)rows_pad * ldl;
-  const long long valid = (long long)n_aux_pad * ldl;
-  const int nch = ldl / MX_KC;
+  const long long total = (long long)rows_pad * ldlk;
+  const int nch = ldlk / MixK<T>::KC;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
-    const int r = (int)(idx / ldl), k = (int)(idx % ldl);
-    const double v = idx < valid ? Lp[idx] : 0.0;
-    const long long ia = FRAG ? mix_frag_a(r, k, nch) : idx;
-    const long long ib = FRAG ? mix_frag_b(r, k, nch) : idx;
-    Lf[ia] = (float)v;
+    const int r = (int)(idx / ldlk), k = (int)(idx % ldlk);
+    const bool in = r < n_aux_pad && k < ldl;
+    const double v = in ? Lp[(long long)r * ldl + k] : 0.0;
+    Lf[mix_frag_a<T>(r, k, nch)] = (float)v;
     typename Mix<T>::E h, l;
-    Mix<T>::split((float)(colscale ? v * (double)colscale[k] : v), h, l);
+    Mix<T>::split((float)(colscale && in ? v * (double)colscale[k] : v), h, l);
+    const long long ib = mix_frag_b<T>(r, k, nch);
     Bhi[ib] = h;
     Blo[ib] = l;
   }
@@ -195,131 +202,6 @@ __global__ void taskscale_kernel(const double *__restrict__ chi_re, const double
   }
 }
 
-// Grid: (n_tiles, F).  Wave w: rows 32*(w/2) .. +32, columns (MX_TC/2)*(w%2)
-// .. +MX_TC/2, i.e. 2 x MX_NB blocks of 16 x 16, Re and Im accumulators (FP32).
-// MFMA layout (16x16x32): lane l supplies A[l%16][8(l/16)+e], B[8(l/16)+e][l%16];
-// output element r of lane l is D[4(l/16)+r][l%16].
-template <class T>
-__global__ void __launch_bounds__(4 * mx_rows<T>(), 512 / (4 * mx_rows<T>()))
-pi_build_mixed_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__restrict__ Bhi,
-                      const typename Mix<T>::E *__restrict__ Blo, int ldl, int n_aux,
-                      const double *__restrict__ chi_re, const double *__restrict__ chi_im,
-                      const float *__restrict__ inv_colscale, const float *__restrict__ tscale,
-                      const int2 *__restrict__ tiles, double2 *__restrict__ G, long long g_stride,
-                      int ldg) {
-  using E = typename Mix<T>::E;
-  using V = typename Mix<T>::V;
-  constexpr int EP = 16 / (int)sizeof(E);  // elements per 16-byte load
-  // B rows padded by 16 bytes (rows stay 16-byte aligned)
-  constexpr int KC = MX_KC, LA = KC + 4, LB = KC + EP;
-  constexpr int TR = mx_rows<T>(), NT = 4 * TR;
-  __shared__ float As[TR * LA];
-  __shared__ E Bh[MX_TC * LB];
-  __shared__ E Bl[MX_TC * LB];
-  __shared__ float Cr[KC], Ci[KC];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lq = lane >> 4;
-  const int2 tb = tiles[blockIdx.x];
-  const int P0 = tb.x * TR, Q0 = tb.y * MX_TC;
-  const int f = blockIdx.y;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * (MX_TC / 2);
-  const float gsc = tscale ? tscale[f] : 1.0f;
-
-  f4 accr[2][MX_NB], acci[2][MX_NB];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < MX_NB; ++b) {
-      accr[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-      acci[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-
-  const double *cr_g = chi_re + (long long)f * ldl;
-  const double *ci_g = chi_im + (long long)f * ldl;
-  for (int kc = 0; kc < ldl; kc += KC) {
-    // A source: TR rows x 32 floats (8 per thread as two float4)
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int idx = it * NT + tid;       // 0 .. 8 TR - 1
-      const int row = idx >> 3, kq = (idx & 7) * 4;
-      const float4 v = *reinterpret_cast<const float4 *>(Lf + (long long)(P0 + row) * ldl + kc + kq);
-      float *dst = As + row * LA + kq;
-      dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
-    }
-    // B: MX_TC rows x 32 elements, hi and lo (16 B per thread and pass)
-#pragma unroll
-    for (int it = 0; it < MX_TC * KC / (EP * NT); ++it) {
-      const int idx = it * NT + tid;
-      const int row = idx / (KC / EP), kq = (idx % (KC / EP)) * EP;
-      const long long off = (long long)(Q0 + row) * ldl + kc + kq;
-      const uint4 vh = *reinterpret_cast<const uint4 *>(Bhi + off);
-      const uint4 vl = *reinterpret_cast<const uint4 *>(Blo + off);
-      *reinterpret_cast<uint4 *>(Bh + row * LB + kq) = vh;
-      *reinterpret_cast<uint4 *>(Bl + row * LB + kq) = vl;
-    }
-    if (tid < KC) {
-      const float s = inv_colscale ? inv_colscale[kc + tid] : 1.0f;
-      Cr[tid] = (float)cr_g[kc + tid] * s * gsc;
-      Ci[tid] = (float)ci_g[kc + tid] * s * gsc;
-    }
-    __syncthreads();
-
-    // A operands: this wave's two row blocks, Re and Im, split hi/lo
-    V arh[2], arl[2], aih[2], ail[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const float *src = As + (wr + 16 * a + li) * LA + 8 * lq;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float lv = src[e];
-        E h, l;
-        Mix<T>::split(lv * Cr[8 * lq + e], h, l);
-        arh[a][e] = h;
-        arl[a][e] = l;
-        Mix<T>::split(lv * Ci[8 * lq + e], h, l);
-        aih[a][e] = h;
-        ail[a][e] = l;
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < MX_NB; ++b) {
-      const int col = wc + 16 * b + li;
-      const V bh = *reinterpret_cast<const V *>(Bh + col * LB + 8 * lq);
-      const V bl = *reinterpret_cast<const V *>(Bl + col * LB + 8 * lq);
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        accr[a][b] = Mix<T>::mfma(arh[a], bh, accr[a][b]);
-        accr[a][b] = Mix<T>::mfma(arh[a], bl, accr[a][b]);
-        accr[a][b] = Mix<T>::mfma(arl[a], bh, accr[a][b]);
-        acci[a][b] = Mix<T>::mfma(aih[a], bh, acci[a][b]);
-        acci[a][b] = Mix<T>::mfma(aih[a], bl, acci[a][b]);
-        acci[a][b] = Mix<T>::mfma(ail[a], bh, acci[a][b]);
-      }
-    }
-    __syncthreads();
-  }
-
-  // upper triangle (col >= row) written with its mirror, as 1 - Pi
-  const double unscale = 1.0 / (double)gsc;
-  double2 *Gf = G + (long long)f * g_stride;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < MX_NB; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = P0 + wr + 16 * a + 4 * lq + r;
-        const int col = Q0 + wc + 16 * b + li;
-        if (row < n_aux && col < n_aux && col >= row) {
-          const double pr = (double)accr[a][b][r] * unscale, pi = (double)acci[a][b][r] * unscale;
-          const double2 v = make_double2((row == col ? 1.0 : 0.0) - pr, -pi);
-          Gf[(long long)row * ldg + col] = v;
-          if (col != row) Gf[(long long)col * ldg + row] = v;
-        }
-      }
-}
-
 // Per-frequency FP32 chi with the column scales 2^-e_k and the frequency scale
 // 2^g folded in (the same float operations as the A operand needs), per K
 // chunk of 32 the 32 Re values then the 32 Im values: cf[f][k / 32][2][32].
@@ -331,30 +213,33 @@ mixed_chi_kernel(const double *__restrict__ chi_re, const double *__restrict__ c
   if (k >= ldl) return;
   const float s = inv_colscale ? inv_colscale[k] : 1.0f;
   const float g = tscale ? tscale[f] : 1.0f;
-  float *o = cf + (long long)f * 2 * ldl + (k / MX_KC) * 2 * MX_KC + k % MX_KC;
+  float *o = cf + (long long)f * 2 * ldl + (k / MX_KSTEP) * 2 * MX_KSTEP + k % MX_KSTEP;
   o[0] = (float)chi_re[(long long)f * ldl + k] * s * g;
-  o[MX_KC] = (float)chi_im[(long long)f * ldl + k] * s * g;
+  o[MX_KSTEP] = (float)chi_im[(long long)f * ldl + k] * s * g;
 }
 
-// The 16-bit forms with the K chunks in a three-stage LDS ring.  One
-// workgroup of 8 waves per 128 x 256 tile and frequency; wave w covers rows
-// 16 w and all 256 columns: 16 blocks of 16 x 16, Re and Im accumulators.
-// Each K chunk of 32 is fetched straight into LDS (buffer_load ... lds, 16
-// bytes per lane at piece base + 16 lane: no registers, no padding) two
-// chunks ahead of its multiply: per wave two 1 KB pieces each of the A rows
-// (FP32 L) and of the split B rows, in operand-fragment order, and the
-// chunk's 64 FP32 chi values (Re, Im).  The stages are separate __shared__
-// objects and the loop is unrolled by three, so each multiply names one stage
-// and each fetch another, and the compiler inserts no waits between them.
+// The Pi build of every mixed form, with the K chunks in a three-stage LDS
+// ring.  One workgroup of 8 waves per 128 x 256 tile and frequency; wave w
+// covers rows 16 w and all 256 columns: 16 blocks of 16 x 16, Re and Im
+// accumulators.  Each K chunk (32 for the 16-bit forms, 64 for FP8) is
+// fetched two chunks ahead of its multiply: per wave two 1 KB pieces of each
+// split B operand (hi, lo) straight into LDS (buffer_load ... lds, 16 bytes
+// per lane at piece base + 16 lane: no registers, no padding) with the
+// chunk's FP32 chi, and the wave's own A rows (FP32 L) into registers, all in
+// operand-fragment order.  The stages are separate __shared__ objects and the
+// loop is unrolled by three, so each multiply names one stage and each fetch
+// another, and the compiler inserts no waits between them.
 // Raw buffer resources (base, no stride, size in bytes; the gfx9 format word):
 // the hardware returns zeros past the size instead of faulting.
 constexpr int BUF_FORMAT_WORD = 0x00020000;
 
-// One K chunk (columns kc .. kc + 32) of the tile's A rows and B rows into the
-// LDS stage, two 1 KB pieces of each buffer per wave: buffer_load ... lds with
-// a loop-invariant per-lane byte offset (voA, voB) and the chunk's offset as
-// the scalar offset.
-// The loads of one K chunk (columns kc .. kc + 32), issued in three parts
+// The A rows of one chunk for one lane: 8 floats per MFMA K step.
+template <class T>
+struct MixAReg {
+  f8v v[MixK<T>::STEPS];
+};
+
+// The loads of one K chunk (columns kc .. kc + KC), issued in three parts
 // spread over the products of the chunk before (a burst of all of them at
 // once holds the waves at the memory issue queue while the MFMA pipes idle).
 // The chunk offset goes into the per-lane offset, which the hardware checks
@@ -363,39 +248,48 @@ constexpr int BUF_FORMAT_WORD = 0x00020000;
 template <class T>
 struct MixFetch {
   using E = typename Mix<T>::E;
+  static constexpr int KC = MixK<T>::KC, AP = 2 * MixK<T>::STEPS;
+  static constexpr int LOADS = 1 + AP + 4;  // loads of one fetch per wave
   __amdgpu_buffer_rsrc_t rA, rBh, rBl, rC;
-  int voA[2], voB[2], wave, lane;
+  int voA[AP], voB[2], wave, lane;
 
-  // part 0: the chunk's chi (64 floats) into the stage's 1 KB of C, by every
-  // wave (the same bytes, so that each wave's own wait covers them; lanes 16
-  // and up read what follows, or zeros: unused), and the wave's own A rows
-  // straight into registers (its lane's 8 floats)
-  __device__ __forceinline__ void part0(f8v &areg, float *C, int kc) const {
+  // part 0: the chunk's chi (2 KC floats) into the stage's 1 KB of C, by every
+  // wave (the same bytes, so that each wave's own wait covers them; the lanes
+  // past the chunk read what follows, or zeros: unused), and the wave's own A
+  // rows straight into registers (its lane's 8 floats per K step)
+  __device__ __forceinline__ void part0(MixAReg<T> &areg, float *C, int kc) const {
     typedef float f4v __attribute__((ext_vector_type(4)));
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rC, C, 16, 16 * lane + kc * 8, 0, 0, 0);
-    const f4v a0 = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[0] + kc * 64, 0, 0));
-    const f4v a1 = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[1] + kc * 64, 0, 0));
-    areg = f8v{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+    for (int st = 0; st < MixK<T>::STEPS; ++st) {
+      const f4v a0 = __builtin_bit_cast(
+          f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[2 * st] + kc * 64, 0, 0));
+      const f4v a1 = __builtin_bit_cast(
+          f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[2 * st + 1] + kc * 64, 0, 0));
+      areg.v[st] = f8v{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+    }
   }
   // parts 1 and 2: the wave's B pieces 2 wave + j (hi and lo) into the stage
   __device__ __forceinline__ void partB(int j, E *Bh, E *Bl, int kc) const {
+    constexpr int PIECE = 1024 / (int)sizeof(E);  // elements of a 1 KB piece
     const int q = 2 * wave + j;
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rBh, Bh + 512 * q, 16, voB[j] + kc * 32, 0, 0, 0);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rBl, Bl + 512 * q, 16, voB[j] + kc * 32, 0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rBh, Bh + PIECE * q, 16, voB[j] + kc * (1024 / KC), 0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rBl, Bl + PIECE * q, 16, voB[j] + kc * (1024 / KC), 0, 0, 0);
   }
-  __device__ __forceinline__ void all(f8v &areg, E *Bh, E *Bl, float *C, int kc) const {
+  __device__ __forceinline__ void all(MixAReg<T> &areg, E *Bh, E *Bl, float *C, int kc) const {
     part0(areg, C, kc);
     partB(0, Bh, Bl, kc);
     partB(1, Bh, Bl, kc);
   }
 };
 
-// Waits until at most one fetch (its 7 loads) of this wave is in flight:
-// s_waitcnt vmcnt(7), the other counters unconstrained (expcnt 7, lgkmcnt 15).
-constexpr int MX_LOADS_PER_FETCH = 7;
+// Waits until at most one fetch (its LOADS loads) of this wave is in flight:
+// s_waitcnt vmcnt(LOADS), the other counters unconstrained (expcnt 7,
+// lgkmcnt 15).
+template <class T>
 __device__ __forceinline__ void mix_wait_one_fetch() {
-  static_assert(MX_LOADS_PER_FETCH == 7, "the wait below encodes vmcnt(7)");
-  __builtin_amdgcn_s_waitcnt(0x0F70 | MX_LOADS_PER_FETCH);
+  static_assert(MixFetch<T>::LOADS < 16, "vmcnt's low field holds 0 .. 15");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | MixFetch<T>::LOADS);
 }
 
 // The workgroup barrier of the K loop, without the memory fence that
@@ -419,7 +313,7 @@ __device__ __forceinline__ f8v ld8(const float *p) {
 }
 
 template <class T>
-__device__ __forceinline__ void split8(f8v x, us8 &hi, us8 &lo) {
+__device__ __forceinline__ void split8(f8v x, typename Mix<T>::V &hi, typename Mix<T>::V &lo) {
   typedef T t8 __attribute__((ext_vector_type(8)));
   const t8 h = __builtin_convertvector(x, t8);
   const f8v r = x - __builtin_convertvector(h, f8v);
@@ -443,6 +337,38 @@ __device__ __forceinline__ void split8<__bf16>(f8v x, us8 &hi, us8 &lo) {
   hi = __builtin_bit_cast(us8, h);
   lo = __builtin_bit_cast(us8, __builtin_convertvector(x - hf, t8));
 }
+// e4m3: pairs converted into the halves of a word (round to nearest even, the
+// same conversions as Mix<e4m3>::split), hi read back per byte
+template <>
+__device__ __forceinline__ void split8<e4m3>(f8v x, uc8 &hi, uc8 &lo) {
+  typedef int i2 __attribute__((ext_vector_type(2)));
+  int h0 = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
+  h0 = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], h0, true);
+  int h1 = __builtin_amdgcn_cvt_pk_fp8_f32(x[4], x[5], 0, false);
+  h1 = __builtin_amdgcn_cvt_pk_fp8_f32(x[6], x[7], h1, true);
+  const f8v hf = f8v{__builtin_amdgcn_cvt_f32_fp8(h0, 0), __builtin_amdgcn_cvt_f32_fp8(h0, 1),
+                     __builtin_amdgcn_cvt_f32_fp8(h0, 2), __builtin_amdgcn_cvt_f32_fp8(h0, 3),
+                     __builtin_amdgcn_cvt_f32_fp8(h1, 0), __builtin_amdgcn_cvt_f32_fp8(h1, 1),
+                     __builtin_amdgcn_cvt_f32_fp8(h1, 2), __builtin_amdgcn_cvt_f32_fp8(h1, 3)};
+  const f8v r = x - hf;
+  int l0 = __builtin_amdgcn_cvt_pk_fp8_f32(r[0], r[1], 0, false);
+  l0 = __builtin_amdgcn_cvt_pk_fp8_f32(r[2], r[3], l0, true);
+  int l1 = __builtin_amdgcn_cvt_pk_fp8_f32(r[4], r[5], 0, false);
+  l1 = __builtin_amdgcn_cvt_pk_fp8_f32(r[6], r[7], l1, true);
+  hi = __builtin_bit_cast(uc8, i2{h0, h1});
+  lo = __builtin_bit_cast(uc8, i2{l0, l1});
+}
+
+// A lane's 16 bytes of a B piece as the operand of K step st.
+template <class T>
+__device__ __forceinline__ typename Mix<T>::V mix_bstep(const uint4 &w, int st) {
+  if constexpr (sizeof(typename Mix<T>::E) == 2) {
+    return __builtin_bit_cast(typename Mix<T>::V, w);
+  } else {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(typename Mix<T>::V, st == 0 ? u2{w.x, w.y} : u2{w.z, w.w});
+  }
+}
 
 // One wave's 16 rows against the 16 column blocks of a stage, in groups of
 // four blocks: a group is skipped when none of its blocks is in [b0, b1)
@@ -450,53 +376,61 @@ __device__ __forceinline__ void split8<__bf16>(f8v x, us8 &hi, us8 &lo) {
 // nothing that is stored, and the two waves of a SIMD share its MFMA pipe, so
 // skipping them shortens the tiles that cross the diagonal).
 template <class T>
-__device__ __forceinline__ void mix_multiply(const f8v &lv, const typename Mix<T>::E *Bh,
+__device__ __forceinline__ void mix_multiply(const MixAReg<T> &lv, const typename Mix<T>::E *Bh,
                                              const typename Mix<T>::E *Bl, const float *C, int lane,
                                              int lq, int b0, int b1, f4 (&accr)[16], f4 (&acci)[16],
-                                             const MixFetch<T> &fetch, f8v &areg_next,
+                                             const MixFetch<T> &fetch, MixAReg<T> &areg_next,
                                              typename Mix<T>::E *Bh_next, typename Mix<T>::E *Bl_next,
                                              float *C_next, int kc_next) {
   using E = typename Mix<T>::E;
   using V = typename Mix<T>::V;
+  constexpr int STEPS = MixK<T>::STEPS, PIECE = 1024 / (int)sizeof(E), EPL = 16 / (int)sizeof(E);
   fetch.part0(areg_next, C_next, kc_next);
-  V arh, arl, aih, ail;
-  {
+  V arh[STEPS], arl[STEPS], aih[STEPS], ail[STEPS];
+#pragma unroll
+  for (int st = 0; st < STEPS; ++st) {
     // 16-byte LDS reads only (a 32-byte read is split by the compiler into
     // accesses it cannot tell apart from the fetch into the other stage, and
-    // it would then wait for that fetch)
-    const f8v cr = ld8(C + 8 * lq), ci = ld8(C + MX_KC + 8 * lq);
-    split8<T>(lv * cr, arh, arl);
-    split8<T>(lv * ci, aih, ail);
+    // it would then wait for that fetch); the chunk's chi is [K step][Re, Im][32]
+    const f8v cr = ld8(C + 64 * st + 8 * lq), ci = ld8(C + 64 * st + 32 + 8 * lq);
+    split8<T>(lv.v[st] * cr, arh[st], arl[st]);
+    split8<T>(lv.v[st] * ci, aih[st], ail[st]);
   }
-  const E *bh_p = Bh + 8 * lane;
-  const E *bl_p = Bl + 8 * lane;
+  const E *bh_p = Bh + EPL * lane;
+  const E *bl_p = Bl + EPL * lane;
   // groups of four column blocks: one uniform branch per group, and a group's
-  // eight LDS reads are issued together ahead of its 24 products (eight
+  // eight LDS reads are issued together ahead of its products (eight
   // independent accumulator chains)
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     if (g == 1 || g == 2) fetch.partB(g - 1, Bh_next, Bl_next, kc_next);
     if (4 * g + 3 >= b0 && 4 * g < b1) {
-      V bh[4], bl[4];
+      uint4 bh[4], bl[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        bh[j] = *reinterpret_cast<const V *>(bh_p + 512 * (4 * g + j));
-        bl[j] = *reinterpret_cast<const V *>(bl_p + 512 * (4 * g + j));
+        bh[j] = *reinterpret_cast<const uint4 *>(bh_p + PIECE * (4 * g + j));
+        bl[j] = *reinterpret_cast<const uint4 *>(bl_p + PIECE * (4 * g + j));
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        accr[4 * g + j] = Mix<T>::mfma(arh, bh[j], accr[4 * g + j]);
-        acci[4 * g + j] = Mix<T>::mfma(aih, bh[j], acci[4 * g + j]);
-      }
+      for (int st = 0; st < STEPS; ++st) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        accr[4 * g + j] = Mix<T>::mfma(arl, bh[j], accr[4 * g + j]);
-        acci[4 * g + j] = Mix<T>::mfma(ail, bh[j], acci[4 * g + j]);
-      }
+        for (int j = 0; j < 4; ++j) {
+          const V h = mix_bstep<T>(bh[j], st);
+          accr[4 * g + j] = Mix<T>::mfma(arh[st], h, accr[4 * g + j]);
+          acci[4 * g + j] = Mix<T>::mfma(aih[st], h, acci[4 * g + j]);
+        }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        accr[4 * g + j] = Mix<T>::mfma(arh, bl[j], accr[4 * g + j]);
-        acci[4 * g + j] = Mix<T>::mfma(aih, bl[j], acci[4 * g + j]);
+        for (int j = 0; j < 4; ++j) {
+          const V h = mix_bstep<T>(bh[j], st);
+          accr[4 * g + j] = Mix<T>::mfma(arl[st], h, accr[4 * g + j]);
+          acci[4 * g + j] = Mix<T>::mfma(ail[st], h, acci[4 * g + j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const V l = mix_bstep<T>(bl[j], st);
+          accr[4 * g + j] = Mix<T>::mfma(arh[st], l, accr[4 * g + j]);
+          acci[4 * g + j] = Mix<T>::mfma(aih[st], l, acci[4 * g + j]);
+        }
       }
     }
   }
@@ -527,15 +461,16 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
                             const int2 *__restrict__ tiles, int n_tiles, int F, int group,
                             double2 *__restrict__ G, long long g_stride, int ldg) {
   using E = typename Mix<T>::E;
-  static_assert(sizeof(E) == 2, "16-bit forms only");
+  constexpr int KC = MixK<T>::KC, AP = 2 * MixK<T>::STEPS;
   // three stages as separate objects (the compiler then needs no wait between
-  // a fetch into one and the reads of another)
+  // a fetch into one and the reads of another); a stage's B pieces are 16 KB
+  // of each split part in every form
   struct Stage {
-    E Bh[MX_TC * MX_KC], Bl[MX_TC * MX_KC];
+    E Bh[MX_TC * KC], Bl[MX_TC * KC];
     float C[256];
   };
   __shared__ Stage S0, S1, S2;
-  f8v R0, R1, R2;  // the A rows of the chunk in each stage (registers)
+  MixAReg<T> R0, R1, R2;  // the A rows of the chunk in each stage (registers)
   // the wave index is uniform: in a scalar register, the LDS bases of the
   // fetches can go to M0
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -553,19 +488,20 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
   if (r_first - Q0 - 15 <= 0) b0 = 0;
   const int b1 = r_first < n_aux ? min(16, (n_aux - Q0 + 15) / 16) : 0;
   // This tile's operands in fragment order (mixed_prep_kernel): A from row
-  // block P0 / 16 on (8 blocks of two 1 KB pieces per chunk), B from row block
+  // block P0 / 16 on (8 blocks of AP 1 KB pieces per chunk), B from row block
   // Q0 / 16 on (16 blocks of one 1 KB piece per chunk), as buffer resources.
   // Wave w fetches A block w (its own 16 rows) and B blocks 2 w, 2 w + 1; lane
   // l of a piece loads its bytes 16 l .. 16 l + 15 and lands at 16 l of the
   // piece in LDS, where the products' lane l reads them (consecutive lanes,
   // consecutive bytes: coalesced, and no LDS bank conflicts).
-  const int nch = ldl / MX_KC;
+  const int nch = (ldl + KC - 1) / KC;  // the operands span nch KC columns
+  constexpr int PIECE = 1024 / (int)sizeof(E);
   const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
-      (void *)(Lf + (long long)(P0 / 16) * nch * 512), 0, 8 * nch * 2048, BUF_FORMAT_WORD);
+      (void *)(Lf + (long long)(P0 / 16) * nch * AP * 256), 0, 8 * nch * AP * 1024, BUF_FORMAT_WORD);
   const __amdgpu_buffer_rsrc_t rBh = __builtin_amdgcn_make_buffer_rsrc(
-      (void *)(Bhi + (long long)(Q0 / 16) * nch * 512), 0, 16 * nch * 1024, BUF_FORMAT_WORD);
+      (void *)(Bhi + (long long)(Q0 / 16) * nch * PIECE), 0, 16 * nch * 1024, BUF_FORMAT_WORD);
   const __amdgpu_buffer_rsrc_t rBl = __builtin_amdgcn_make_buffer_rsrc(
-      (void *)(Blo + (long long)(Q0 / 16) * nch * 512), 0, 16 * nch * 1024, BUF_FORMAT_WORD);
+      (void *)(Blo + (long long)(Q0 / 16) * nch * PIECE), 0, 16 * nch * 1024, BUF_FORMAT_WORD);
   const __amdgpu_buffer_rsrc_t rC = __builtin_amdgcn_make_buffer_rsrc((void *)cf, 0, 2 * ldl * 4,
                                                                       BUF_FORMAT_WORD);
   MixFetch<T> fetch;
@@ -576,10 +512,9 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
   fetch.wave = wave;
   fetch.lane = lane;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    fetch.voA[j] = (wave * nch * 2 + j) * 1024 + 16 * lane;
-    fetch.voB[j] = (2 * wave + j) * nch * 1024 + 16 * lane;
-  }
+  for (int j = 0; j < AP; ++j) fetch.voA[j] = (wave * nch * AP + j) * 1024 + 16 * lane;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) fetch.voB[j] = (2 * wave + j) * nch * 1024 + 16 * lane;
 
   f4 accr[16], acci[16];
 #pragma unroll
@@ -599,20 +534,20 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
 #define MX_MUL(S, R, N, RN, kn, bend) \
   mix_multiply<T>(R, S.Bh, S.Bl, S.C, lane, lq, b0, bend, accr, acci, fetch, RN, N.Bh, N.Bl, N.C, kn)
   fetch.all(R0, S0.Bh, S0.Bl, S0.C, 0);
-  fetch.all(R1, S1.Bh, S1.Bl, S1.C, MX_KC);
+  fetch.all(R1, S1.Bh, S1.Bl, S1.C, KC);
   for (int c = 0; c < nch; c += 3) {
     // a step past the last chunk multiplies nothing (no column block below
     // 0) but still fetches, so that the loads in flight stay what the waits
     // count and no fetch sits in a branch
-    mix_wait_one_fetch();
+    mix_wait_one_fetch<T>();
     mix_barrier();
-    MX_MUL(S0, R0, S2, R2, (c + 2) * MX_KC, b1);
-    mix_wait_one_fetch();
+    MX_MUL(S0, R0, S2, R2, (c + 2) * KC, b1);
+    mix_wait_one_fetch<T>();
     mix_barrier();
-    MX_MUL(S1, R1, S0, R0, (c + 3) * MX_KC, c + 1 < nch ? b1 : 0);
-    mix_wait_one_fetch();
+    MX_MUL(S1, R1, S0, R0, (c + 3) * KC, c + 1 < nch ? b1 : 0);
+    mix_wait_one_fetch<T>();
     mix_barrier();
-    MX_MUL(S2, R2, S1, R1, (c + 4) * MX_KC, c + 2 < nch ? b1 : 0);
+    MX_MUL(S2, R2, S1, R1, (c + 4) * KC, c + 2 < nch ? b1 : 0);
   }
   __builtin_amdgcn_s_waitcnt(0);  // no fetch lands after the workgroup's end
 #undef MX_MUL
@@ -636,26 +571,26 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
 }
 
 // ---------------------------------------------------------------------------
-void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, float *Lf,
-                       void *Bhi, void *Blo, float *colscale, float *inv_colscale, float *acol,
-                       hipStream_t stream) {
-  long long blocks = ((long long)rows_pad * ldl + 255) / 256;
+void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, int ldlk,
+                       float *Lf, void *Bhi, void *Blo, float *colscale, float *inv_colscale,
+                       float *acol, hipStream_t stream) {
+  long long blocks = ((long long)rows_pad * ldlk + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (prec == 2) {
     colscale_kernel<<<(ldl + 255) / 256, 256, 0, stream>>>(Lp, n_aux_pad, ldl, Mix<_Float16>::TARGET,
                                                             colscale, inv_colscale, acol);
     mixed_prep_kernel<_Float16><<<(unsigned)blocks, 256, 0, stream>>>(
-        Lp, n_aux_pad, rows_pad, ldl, colscale, Lf, static_cast<unsigned short *>(Bhi),
+        Lp, n_aux_pad, rows_pad, ldl, ldlk, colscale, Lf, static_cast<unsigned short *>(Bhi),
         static_cast<unsigned short *>(Blo));
   } else if (prec == 3) {
     colscale_kernel<<<(ldl + 255) / 256, 256, 0, stream>>>(Lp, n_aux_pad, ldl, Mix<e4m3>::TARGET,
                                                             colscale, inv_colscale, acol);
     mixed_prep_kernel<e4m3><<<(unsigned)blocks, 256, 0, stream>>>(
-        Lp, n_aux_pad, rows_pad, ldl, colscale, Lf, static_cast<unsigned char *>(Bhi),
+        Lp, n_aux_pad, rows_pad, ldl, ldlk, colscale, Lf, static_cast<unsigned char *>(Bhi),
         static_cast<unsigned char *>(Blo));
   } else {
     mixed_prep_kernel<__bf16><<<(unsigned)blocks, 256, 0, stream>>>(
-        Lp, n_aux_pad, rows_pad, ldl, nullptr, Lf, static_cast<unsigned short *>(Bhi),
+        Lp, n_aux_pad, rows_pad, ldl, ldlk, nullptr, Lf, static_cast<unsigned short *>(Bhi),
         static_cast<unsigned short *>(Blo));
   }
 }
@@ -665,23 +600,24 @@ void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const voi
                            const float *inv_colscale, const float *acol, float *tscale, float *chi_f32,
                            int F, const int2 *tiles, int n_tiles, double2 *G, long long g_stride,
                            int ldg, hipStream_t stream) {
-  dim3 grid(n_tiles, F);
-  if (prec == 3) {
-    taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, Mix<e4m3>::TARGET, acol, tscale);
-    pi_build_mixed_kernel<e4m3><<<grid, 4 * mx_rows<e4m3>(), 0, stream>>>(
-        Lf, static_cast<const unsigned char *>(Bhi), static_cast<const unsigned char *>(Blo), ldl,
-        n_aux, chi_re, chi_im, inv_colscale, tscale, tiles, G, g_stride, ldg);
-    return;
-  }
-  const bool fp16 = prec == 2;
-  if (fp16) taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl, Mix<_Float16>::TARGET, acol, tscale);
+  // FP16 and FP8 scale each frequency's A operand by a power of two (undone on
+  // the result) and fold the column scales into chi; BF16 needs neither
+  const bool scaled = prec == 2 || prec == 3;
+  if (scaled)
+    taskscale_kernel<<<F, 256, 0, stream>>>(chi_re, chi_im, ldl,
+                                            prec == 3 ? Mix<e4m3>::TARGET : Mix<_Float16>::TARGET, acol,
+                                            tscale);
   mixed_chi_kernel<<<dim3((ldl + 255) / 256, F), 256, 0, stream>>>(
-      chi_re, chi_im, ldl, fp16 ? inv_colscale : nullptr, fp16 ? tscale : nullptr, chi_f32);
+      chi_re, chi_im, ldl, scaled ? inv_colscale : nullptr, scaled ? tscale : nullptr, chi_f32);
   // (tile, frequency-group) blocks, rounded up to a whole turn of the XCDs
   const int group = F < 32 ? F : 32;
   const long long blocks = (long long)n_tiles * ((F + group - 1) / group);
   const long long wgs = (blocks + MX_NXCD - 1) / MX_NXCD * MX_NXCD * group;
-  if (fp16)
+  if (prec == 3)
+    pi_build_mixed_async_kernel<e4m3><<<(unsigned)wgs, 512, 0, stream>>>(
+        Lf, static_cast<const unsigned char *>(Bhi), static_cast<const unsigned char *>(Blo), ldl,
+        n_aux, chi_f32, tscale, tiles, n_tiles, F, group, G, g_stride, ldg);
+  else if (prec == 2)
     pi_build_mixed_async_kernel<_Float16><<<(unsigned)wgs, 512, 0, stream>>>(
         Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
         n_aux, chi_f32, tscale, tiles, n_tiles, F, group, G, g_stride, ldg);
