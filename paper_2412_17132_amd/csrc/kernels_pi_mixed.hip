@@ -469,8 +469,8 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
     E Bh[MX_TC * KC], Bl[MX_TC * KC];
     float C[256];
   };
-  __shared__ Stage S0, S1, S2;
-  MixAReg<T> R0, R1, R2;  // the A rows of the chunk in each stage (registers)
+  __shared__ Stage S0, S1, S2, S3;
+  MixAReg<T> R0, R1, R2, R3;  // the A rows of the chunk in each stage (registers)
   // the wave index is uniform: in a scalar register, the LDS bases of the
   // fetches can go to M0
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -522,32 +522,30 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
     accr[b] = f4{0.f, 0.f, 0.f, 0.f};
     acci[b] = f4{0.f, 0.f, 0.f, 0.f};
   }
-  // Three stages: chunk c is in stage c % 3.  Step c waits for its own fetch
-  // of chunk c (the fetch of chunk c + 1 may still be in flight), meets the
-  // other waves at the barrier (every wave's part of chunk c has landed, and
-  // every wave has multiplied chunk c - 1, so its stage is free) and
-  // multiplies chunk c, issuing the fetch of chunk c + 2 into that stage
-  // between its column groups.  Every step fetches (the compiler then tells
-  // the stages apart and adds no waits of its own): the two fetches past the
-  // last chunk read the rows' next bytes or zeros into stages that are not
-  // multiplied.
+  // Four stages, two chunks per barrier: chunk c is in stage c % 4.  A
+  // double step waits for all of this wave's loads (chunks c and c + 1),
+  // meets the other waves at the barrier (every wave's part of both has
+  // landed, and every wave has multiplied chunks c - 2 and c - 1, so their
+  // stages are free) and multiplies c and c + 1, issuing the fetches of
+  // c + 2 and c + 3 into those stages between their column groups.  Every
+  // step fetches (the compiler then tells the stages apart and adds no waits
+  // of its own): the fetches past the last chunk read the rows' next bytes or
+  // zeros into stages that are not multiplied.
 #define MX_MUL(S, R, N, RN, kn, bend) \
   mix_multiply<T>(R, S.Bh, S.Bl, S.C, lane, lq, b0, bend, accr, acci, fetch, RN, N.Bh, N.Bl, N.C, kn)
   fetch.all(R0, S0.Bh, S0.Bl, S0.C, 0);
   fetch.all(R1, S1.Bh, S1.Bl, S1.C, KC);
-  for (int c = 0; c < nch; c += 3) {
+  for (int c = 0; c < nch; c += 4) {
     // a step past the last chunk multiplies nothing (no column block below
-    // 0) but still fetches, so that the loads in flight stay what the waits
-    // count and no fetch sits in a branch
-    mix_wait_one_fetch<T>();
+    // 0) but still fetches, so that no fetch sits in a branch
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks c, c + 1
     mix_barrier();
     MX_MUL(S0, R0, S2, R2, (c + 2) * KC, b1);
-    mix_wait_one_fetch<T>();
+    MX_MUL(S1, R1, S3, R3, (c + 3) * KC, c + 1 < nch ? b1 : 0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     mix_barrier();
-    MX_MUL(S1, R1, S0, R0, (c + 3) * KC, c + 1 < nch ? b1 : 0);
-    mix_wait_one_fetch<T>();
-    mix_barrier();
-    MX_MUL(S2, R2, S1, R1, (c + 4) * KC, c + 2 < nch ? b1 : 0);
+    MX_MUL(S2, R2, S0, R0, (c + 4) * KC, c + 2 < nch ? b1 : 0);
+    MX_MUL(S3, R3, S1, R1, (c + 5) * KC, c + 3 < nch ? b1 : 0);
   }
   __builtin_amdgcn_s_waitcnt(0);  // no fetch lands after the workgroup's end
 #undef MX_MUL
