@@ -38,10 +38,10 @@ void launch_pi_build_f64(const double *Lp, int ldl, int n_aux, const double *chi
 // Mixed-precision Pi build.  Tiles are mixed_tile_rows(prec) x MX_TILE_COLS
 // blocks (128 x 256); the split operands have their rows padded to a multiple
 // of MX_TILE_COLS and their columns to mixed_ldl(prec, ldl) (the form's K
-// chunk: 32 for the 16-bit forms, 64 for FP8).
+// chunk: 32 for the 16-bit forms; for FP8 a pair of 64-wide chunks, 128).
 constexpr int MX_TILE_COLS = 256;
 constexpr int mixed_tile_rows(int) { return 128; }
-constexpr int mixed_ldl(int prec, int ldl) { return prec == 3 ? (ldl + 63) / 64 * 64 : ldl; }
+constexpr int mixed_ldl(int prec, int ldl) { return prec == 3 ? (ldl + 127) / 128 * 128 : ldl; }
 // prec 1 BF16X3, 2 FP16X3, 3 FP8X3; Bhi / Blo hold 16-bit (1, 2) or 8-bit (3)
 // elements, rows_pad x ldlk of them (ldlk = mixed_ldl(prec, ldl)).
 void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, int ldlk,

@@ -94,13 +94,15 @@ struct Mix<e4m3> {
 // ---------------------------------------------------------------------------
 // K per chunk of the Pi build: one MFMA K step (32) for the 16-bit forms, two
 // for FP8, so that a lane's 16-byte load holds 8 one-byte values of each step.
+// FP8 takes its chunks in pairs (one K = 128 product per pair), so its
+// operands span a whole number of pairs (KPAD columns).
 template <class T>
 struct MixK {
-  static constexpr int KC = 32, STEPS = 1;
+  static constexpr int KC = 32, STEPS = 1, KPAD = 32;
 };
 template <>
 struct MixK<e4m3> {
-  static constexpr int KC = 64, STEPS = 2;
+  static constexpr int KC = 64, STEPS = 2, KPAD = 128;
 };
 
 // Per-call preparation: FP32 copy of L (A source) and the split B operand,
@@ -436,6 +438,85 @@ __device__ __forceinline__ void mix_multiply(const MixAReg<T> &lv, const typenam
   }
 }
 
+// FP8: two K chunks (a, b) at once, each lane's 32 bytes of A and of B being
+// chunk a's 16 then chunk b's 16, so that one v_mfma_f32_16x16x128_f8f6f4
+// (E4M3 operands, no block scales) replaces four K = 32 products; it issues
+// at twice the rate of the K = 32 FP8 form.  A lane's 16 bytes of a chunk
+// hold the same 16 K indices in A (8 per step, split from its FP32 rows) as
+// in B (the fragment order above), and the instruction pairs byte i of an A
+// lane with byte i of the B lane of the same K group, so the 128-term sums
+// are the chunks' dot products.  Column blocks in groups of two (the K = 128
+// operands take twice the registers of the K = 64 ones).
+typedef int i8v __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ i8v mix_cat(uc8 a0, uc8 a1, uc8 b0, uc8 b1) {
+  typedef int i2 __attribute__((ext_vector_type(2)));
+  const i2 w = __builtin_bit_cast(i2, a0), x = __builtin_bit_cast(i2, a1);
+  const i2 y = __builtin_bit_cast(i2, b0), z = __builtin_bit_cast(i2, b1);
+  return i8v{w[0], w[1], x[0], x[1], y[0], y[1], z[0], z[1]};
+}
+__device__ __forceinline__ i8v mix_cat(const uint4 &a, const uint4 &b) {
+  return i8v{(int)a.x, (int)a.y, (int)a.z, (int)a.w, (int)b.x, (int)b.y, (int)b.z, (int)b.w};
+}
+__device__ __forceinline__ f4 mix_mfma128(const i8v &a, const i8v &b, f4 c) {
+  // format 0 (E4M3) for both operands; zero scale operands select the
+  // unscaled instruction
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+}
+
+__device__ __forceinline__ void mix_multiply_pair(
+    const MixAReg<e4m3> &la, const MixAReg<e4m3> &lb, const unsigned char *Bh_a,
+    const unsigned char *Bl_a, const float *C_a, const unsigned char *Bh_b, const unsigned char *Bl_b,
+    const float *C_b, int lane, int lq, int b0, int b1, f4 (&accr)[16], f4 (&acci)[16],
+    const MixFetch<e4m3> &fetch, MixAReg<e4m3> &an_a, MixAReg<e4m3> &an_b, unsigned char *Bhn_a,
+    unsigned char *Bln_a, float *Cn_a, unsigned char *Bhn_b, unsigned char *Bln_b, float *Cn_b,
+    int kc_next) {
+  constexpr int KC = MixK<e4m3>::KC;
+  fetch.part0(an_a, Cn_a, kc_next);
+  fetch.part0(an_b, Cn_b, kc_next + KC);
+  uc8 rh[4], rl[4], ih[4], il[4];  // [chunk a step 0, a 1, b 0, b 1]
+#pragma unroll
+  for (int st = 0; st < 2; ++st) {
+    split8<e4m3>(la.v[st] * ld8(C_a + 64 * st + 8 * lq), rh[st], rl[st]);
+    split8<e4m3>(la.v[st] * ld8(C_a + 64 * st + 32 + 8 * lq), ih[st], il[st]);
+    split8<e4m3>(lb.v[st] * ld8(C_b + 64 * st + 8 * lq), rh[2 + st], rl[2 + st]);
+    split8<e4m3>(lb.v[st] * ld8(C_b + 64 * st + 32 + 8 * lq), ih[2 + st], il[2 + st]);
+  }
+  const i8v AH = mix_cat(rh[0], rh[1], rh[2], rh[3]), AL = mix_cat(rl[0], rl[1], rl[2], rl[3]);
+  const i8v IH = mix_cat(ih[0], ih[1], ih[2], ih[3]), IL = mix_cat(il[0], il[1], il[2], il[3]);
+  const int lo = 16 * lane;
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    if (g == 1) fetch.partB(0, Bhn_a, Bln_a, kc_next);
+    if (g == 2) fetch.partB(1, Bhn_a, Bln_a, kc_next);
+    if (g == 3) fetch.partB(0, Bhn_b, Bln_b, kc_next + KC);
+    if (g == 4) fetch.partB(1, Bhn_b, Bln_b, kc_next + KC);
+    if (2 * g + 1 >= b0 && 2 * g < b1) {
+      i8v bh[2], bl[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int o = 1024 * (2 * g + j) + lo;
+        bh[j] = mix_cat(*reinterpret_cast<const uint4 *>(Bh_a + o), *reinterpret_cast<const uint4 *>(Bh_b + o));
+        bl[j] = mix_cat(*reinterpret_cast<const uint4 *>(Bl_a + o), *reinterpret_cast<const uint4 *>(Bl_b + o));
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        accr[2 * g + j] = mix_mfma128(AH, bh[j], accr[2 * g + j]);
+        acci[2 * g + j] = mix_mfma128(IH, bh[j], acci[2 * g + j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        accr[2 * g + j] = mix_mfma128(AL, bh[j], accr[2 * g + j]);
+        acci[2 * g + j] = mix_mfma128(IL, bh[j], acci[2 * g + j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        accr[2 * g + j] = mix_mfma128(AH, bl[j], accr[2 * g + j]);
+        acci[2 * g + j] = mix_mfma128(IH, bl[j], acci[2 * g + j]);
+      }
+    }
+  }
+}
+
 // Workgroup -> (tile, frequency) so that the workgroups one XCD holds at a
 // time share a tile: workgroups are dispatched round-robin over the 8 XCDs,
 // and each XCD's consecutive workgroups take one tile for `group` consecutive
@@ -494,7 +575,8 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
   // l of a piece loads its bytes 16 l .. 16 l + 15 and lands at 16 l of the
   // piece in LDS, where the products' lane l reads them (consecutive lanes,
   // consecutive bytes: coalesced, and no LDS bank conflicts).
-  const int nch = (ldl + KC - 1) / KC;  // the operands span nch KC columns
+  constexpr int KPAD = MixK<T>::KPAD;
+  const int nch = (ldl + KPAD - 1) / KPAD * (KPAD / KC);  // the operands span nch KC columns
   constexpr int PIECE = 1024 / (int)sizeof(E);
   const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
       (void *)(Lf + (long long)(P0 / 16) * nch * AP * 256), 0, 8 * nch * AP * 1024, BUF_FORMAT_WORD);
@@ -535,18 +617,30 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
   mix_multiply<T>(R, S.Bh, S.Bl, S.C, lane, lq, b0, bend, accr, acci, fetch, RN, N.Bh, N.Bl, N.C, kn)
   fetch.all(R0, S0.Bh, S0.Bl, S0.C, 0);
   fetch.all(R1, S1.Bh, S1.Bl, S1.C, KC);
+#define MX_MUL2(SA, SB, RA, RB, NA, NB, RNA, RNB, kn, bend)                                     \
+  mix_multiply_pair(RA, RB, SA.Bh, SA.Bl, SA.C, SB.Bh, SB.Bl, SB.C, lane, lq, b0, bend, accr, acci, \
+                    fetch, RNA, RNB, NA.Bh, NA.Bl, NA.C, NB.Bh, NB.Bl, NB.C, kn)
   for (int c = 0; c < nch; c += 4) {
     // a step past the last chunk multiplies nothing (no column block below
     // 0) but still fetches, so that no fetch sits in a branch
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks c, c + 1
     mix_barrier();
-    MX_MUL(S0, R0, S2, R2, (c + 2) * KC, b1);
-    MX_MUL(S1, R1, S3, R3, (c + 3) * KC, c + 1 < nch ? b1 : 0);
+    if constexpr (MixK<T>::KPAD == 2 * KC) {  // FP8: nch is even, a pair at a time
+      MX_MUL2(S0, S1, R0, R1, S2, S3, R2, R3, (c + 2) * KC, b1);
+    } else {
+      MX_MUL(S0, R0, S2, R2, (c + 2) * KC, b1);
+      MX_MUL(S1, R1, S3, R3, (c + 3) * KC, c + 1 < nch ? b1 : 0);
+    }
     __builtin_amdgcn_s_waitcnt(0x0F70);
     mix_barrier();
-    MX_MUL(S2, R2, S0, R0, (c + 4) * KC, c + 2 < nch ? b1 : 0);
-    MX_MUL(S3, R3, S1, R1, (c + 5) * KC, c + 3 < nch ? b1 : 0);
+    if constexpr (MixK<T>::KPAD == 2 * KC) {
+      MX_MUL2(S2, S3, R2, R3, S0, S1, R0, R1, (c + 4) * KC, c + 2 < nch ? b1 : 0);
+    } else {
+      MX_MUL(S2, R2, S0, R0, (c + 4) * KC, c + 2 < nch ? b1 : 0);
+      MX_MUL(S3, R3, S1, R1, (c + 5) * KC, c + 3 < nch ? b1 : 0);
+    }
   }
+#undef MX_MUL2
   __builtin_amdgcn_s_waitcnt(0);  // no fetch lands after the workgroup's end
 #undef MX_MUL
 
