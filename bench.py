@@ -488,7 +488,7 @@ def _compare_solves(ref, res, eta, n_out, d_omega):
     solves from another (both {core: (out, A, z)})."""
     import numpy as np
     from workloads import EV_PER_HA
-    deq, worst, lowest, rels = [], 0.0, 0.0, []
+    deq, worst, lowest, rels, by_core = [], 0.0, 0.0, [], []
     for c, (out, A, z) in res.items():
         if c not in ref:
             continue
@@ -503,13 +503,16 @@ def _compare_solves(ref, res, eta, n_out, d_omega):
             if pm:
                 worst = max(worst, float(np.min(np.abs(np.asarray(pm) - p))))
         if pr and pm:  # the lowest-lying satellite (closest to the QP peak)
-            lowest = max(lowest, float(np.min(np.abs(np.asarray(pm) - max(pr)))))
+            d = float(np.min(np.abs(np.asarray(pm) - max(pr))))
+            lowest = max(lowest, d)
+            by_core.append(round(d * EV_PER_HA * 1e3, 3))
         if out.get("sigma_c") is not None and r_out.get("sigma_c") is not None:
             rels.append(_sigma_rel(r_out, out))
     rec = {"cores_compared": len(deq),
            "e_qp_max_dev_mev": float(max(deq) * EV_PER_HA * 1e3) if deq else None,
            "satellite_max_shift_mev": worst * EV_PER_HA * 1e3,
-           "lowest_satellite_shift_mev": lowest * EV_PER_HA * 1e3}
+           "lowest_satellite_shift_mev": lowest * EV_PER_HA * 1e3,
+           "lowest_satellite_shift_mev_by_core": by_core}
     if rels:
         allr = np.concatenate(rels)
         rec["sigma_c_rel_dev"] = {"max": float(allr.max()), "median": float(np.median(allr))}

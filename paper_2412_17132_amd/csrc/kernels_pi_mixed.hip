@@ -372,8 +372,11 @@ __device__ __forceinline__ typename Mix<T>::V mix_bstep(const uint4 &w, int st) 
   }
 }
 
+// Column blocks per skip group of the 16-bit forms.
+constexpr int MX_BGROUP = 4;
+
 // One wave's 16 rows against the 16 column blocks of a stage, in groups of
-// four blocks: a group is skipped when none of its blocks is in [b0, b1)
+// MX_BGROUP blocks: a group is skipped when none of its blocks is in [b0, b1)
 // (wave-uniform bounds: blocks wholly below the diagonal or past n_aux produce
 // nothing that is stored, and the two waves of a SIMD share its MFMA pipe, so
 // skipping them shortens the tiles that cross the diagonal).
@@ -400,38 +403,39 @@ __device__ __forceinline__ void mix_multiply(const MixAReg<T> &lv, const typenam
   }
   const E *bh_p = Bh + EPL * lane;
   const E *bl_p = Bl + EPL * lane;
-  // groups of four column blocks: one uniform branch per group, and a group's
-  // eight LDS reads are issued together ahead of its products (eight
+  // groups of NG column blocks: one uniform branch per group, and a group's
+  // 2 NG LDS reads are issued together ahead of its products (2 NG
   // independent accumulator chains)
+  constexpr int NG = MX_BGROUP, NGR = 16 / NG;
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    if (g == 1 || g == 2) fetch.partB(g - 1, Bh_next, Bl_next, kc_next);
-    if (4 * g + 3 >= b0 && 4 * g < b1) {
-      uint4 bh[4], bl[4];
+  for (int g = 0; g < NGR; ++g) {
+    if (g == NGR / 4 || g == NGR / 2) fetch.partB(g == NGR / 4 ? 0 : 1, Bh_next, Bl_next, kc_next);
+    if (NG * g + NG - 1 >= b0 && NG * g < b1) {
+      uint4 bh[NG], bl[NG];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        bh[j] = *reinterpret_cast<const uint4 *>(bh_p + PIECE * (4 * g + j));
-        bl[j] = *reinterpret_cast<const uint4 *>(bl_p + PIECE * (4 * g + j));
+      for (int j = 0; j < NG; ++j) {
+        bh[j] = *reinterpret_cast<const uint4 *>(bh_p + PIECE * (NG * g + j));
+        bl[j] = *reinterpret_cast<const uint4 *>(bl_p + PIECE * (NG * g + j));
       }
 #pragma unroll
       for (int st = 0; st < STEPS; ++st) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NG; ++j) {
           const V h = mix_bstep<T>(bh[j], st);
-          accr[4 * g + j] = Mix<T>::mfma(arh[st], h, accr[4 * g + j]);
-          acci[4 * g + j] = Mix<T>::mfma(aih[st], h, acci[4 * g + j]);
+          accr[NG * g + j] = Mix<T>::mfma(arh[st], h, accr[NG * g + j]);
+          acci[NG * g + j] = Mix<T>::mfma(aih[st], h, acci[NG * g + j]);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NG; ++j) {
           const V h = mix_bstep<T>(bh[j], st);
-          accr[4 * g + j] = Mix<T>::mfma(arl[st], h, accr[4 * g + j]);
-          acci[4 * g + j] = Mix<T>::mfma(ail[st], h, acci[4 * g + j]);
+          accr[NG * g + j] = Mix<T>::mfma(arl[st], h, accr[NG * g + j]);
+          acci[NG * g + j] = Mix<T>::mfma(ail[st], h, acci[NG * g + j]);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NG; ++j) {
           const V l = mix_bstep<T>(bl[j], st);
-          accr[4 * g + j] = Mix<T>::mfma(arh[st], l, accr[4 * g + j]);
-          acci[4 * g + j] = Mix<T>::mfma(aih[st], l, acci[4 * g + j]);
+          accr[NG * g + j] = Mix<T>::mfma(arh[st], l, accr[NG * g + j]);
+          acci[NG * g + j] = Mix<T>::mfma(aih[st], l, acci[NG * g + j]);
         }
       }
     }
