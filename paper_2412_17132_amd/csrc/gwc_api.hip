@@ -367,13 +367,13 @@ std::vector<int2> mixed_tiles(int N, int prec) {
   return mt;
 }
 
-// Device bytes of the split operands of one precision (FP32 L, hi and lo
-// parts in 16-bit slots, column scales, tile list), rows padded to 256 and
-// columns to the form's K chunk.
+// Device bytes of the split operands of one precision (the A source L, hi and
+// lo parts, column scales, tile list), rows padded to 256 and columns to the
+// form's K chunk.
 size_t split_operand_bytes(const ResidentSystem &rs, int prec) {
   const int rows_pad = (int)round_up(rs.N, MX_TILE_COLS);
   const size_t elems = (size_t)rows_pad * mixed_ldl(prec, rs.ldl);
-  return elems * (sizeof(float) + 2 * sizeof(unsigned short)) + 3 * (size_t)rs.ldl * sizeof(float) +
+  return elems * (mixed_a_bytes(prec) + 2 * mixed_b_bytes(prec)) + 3 * (size_t)rs.ldl * sizeof(float) +
          mixed_tiles(rs.N, prec).size() * sizeof(int2);
 }
 
@@ -394,14 +394,14 @@ const MixedOperands &mixed_operands(ResidentSystem &rs, int prec, hipStream_t s,
   const int rows_pad = (int)round_up(rs.N, MX_TILE_COLS);
   const int ldlk = mixed_ldl(prec, rs.ldl);
   const size_t elems = (size_t)rows_pad * ldlk;
-  m.Lf.alloc(elems * sizeof(float));
-  m.Bh.alloc(elems * sizeof(unsigned short));
-  m.Bl.alloc(elems * sizeof(unsigned short));
+  m.Lf.alloc(elems * mixed_a_bytes(prec));
+  m.Bh.alloc(elems * mixed_b_bytes(prec));
+  m.Bl.alloc(elems * mixed_b_bytes(prec));
   m.cs.alloc(rs.ldl * sizeof(float));
   m.ics.alloc(rs.ldl * sizeof(float));
   m.acol.alloc(rs.ldl * sizeof(float));
   launch_mixed_prep(prec, rs.d_L.as<double>(), rs.n_aux_pad, rows_pad, rs.ldl, ldlk,
-                    m.Lf.as<float>(), m.Bh.p, m.Bl.p, m.cs.as<float>(), m.ics.as<float>(),
+                    m.Lf.p, m.Bh.p, m.Bl.p, m.cs.as<float>(), m.ics.as<float>(),
                     m.acol.as<float>(), s);
   const std::vector<int2> mt = mixed_tiles(rs.N, prec);
   upload(m.tiles, mt, s);
@@ -500,7 +500,7 @@ void run_screening(ResidentSystem &rs, const MixedOperands *mx, int precision, c
                           rs.d_tiles.as<int2>(), rs.n_tiles, dG.as<double2>(), (long long)mat_elems,
                           ldg, s);
     } else {
-      launch_pi_build_mixed(precision, mx->Lf.as<float>(), mx->Bh.p, mx->Bl.p, rs.ldl, N,
+      launch_pi_build_mixed(precision, mx->Lf.p, mx->Bh.p, mx->Bl.p, rs.ldl, N,
                             dchr.as<double>(), dchi.as<double>(),
                             precision != GWC_PREC_BF16X3 ? mx->ics.as<float>() : nullptr,
                             mx->acol.as<float>(), dts.as<float>(), dcf.as<float>(), Fb, mx->tiles.as<int2>(),

@@ -43,12 +43,16 @@ constexpr int MX_TILE_COLS = 256;
 constexpr int mixed_tile_rows(int) { return 128; }
 constexpr int mixed_ldl(int prec, int ldl) { return prec == 3 ? (ldl + 127) / 128 * 128 : ldl; }
 // prec 1 BF16X3, 2 FP16X3, 3 FP8X3; Bhi / Blo hold 16-bit (1, 2) or 8-bit (3)
-// elements, rows_pad x ldlk of them (ldlk = mixed_ldl(prec, ldl)).
+// elements, rows_pad x ldlk of them (ldlk = mixed_ldl(prec, ldl)); Lf, the
+// A operand's source, as many FP32 values of L (1, 2) or FP16 values of L
+// times its column scales (3).
+constexpr int mixed_a_bytes(int prec) { return prec == 3 ? 2 : 4; }
+constexpr int mixed_b_bytes(int prec) { return prec == 3 ? 1 : 2; }
 void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, int ldlk,
-                       float *Lf, void *Bhi, void *Blo, float *colscale, float *inv_colscale,
+                       void *Lf, void *Bhi, void *Blo, float *colscale, float *inv_colscale,
                        float *acol, hipStream_t stream);
 // chi_f32 is a workspace of F x 2 x ldl floats (the 16-bit forms' scaled FP32 chi).
-void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const void *Blo, int ldl,
+void launch_pi_build_mixed(int prec, const void *Lf, const void *Bhi, const void *Blo, int ldl,
                            int n_aux, const double *chi_re, const double *chi_im,
                            const float *inv_colscale, const float *acol, float *tscale, float *chi_f32,
                            int F, const int2 *tiles, int n_tiles, double2 *G, long long g_stride,

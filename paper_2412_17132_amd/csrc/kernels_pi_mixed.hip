@@ -105,6 +105,22 @@ struct MixK<e4m3> {
   static constexpr int KC = 64, STEPS = 2, KPAD = 128;
 };
 
+// Source of the A operand L chi: FP32 L for the 16-bit forms (their split
+// keeps about 16 or 22 bits of A); for FP8, whose split keeps about 8, FP16
+// L with the column scales 2^e_k applied (the largest |value| of a column in
+// [2^7, 2^8), so that 11 significant bits hold down to 2^-21 of it), half the
+// bytes per chunk.  AP: 1 KB pieces per 16-row block and chunk.
+template <class T>
+struct MixA {
+  using E = float;
+  static constexpr int AP = 2 * MixK<T>::STEPS;
+};
+template <>
+struct MixA<e4m3> {
+  using E = _Float16;
+  static constexpr int AP = MixK<e4m3>::STEPS;
+};
+
 // Per-call preparation: FP32 copy of L (A source) and the split B operand,
 // rows beyond n_aux_pad and columns beyond ldl zero (the operands span ldlk
 // columns, a multiple of the form's chunk).  For FP16 and FP8 each column k
@@ -118,8 +134,10 @@ struct MixK<e4m3> {
 // q = k mod 32,
 //   B: 64 lanes x 16 bytes; lane li + 16 (q / 8) holds row 16 rb + li, as
 //      element 8 s + q mod 8 of its 16 bytes;
-//   A: 2 STEPS pieces of 64 lanes x 4 floats; lane li + 16 (q / 8) of piece
-//      2 s + (q mod 8) / 4 holds row 16 rb + li, as float q mod 4.
+//   A (FP32): 2 STEPS pieces of 64 lanes x 4 floats; lane li + 16 (q / 8) of
+//      piece 2 s + (q mod 8) / 4 holds row 16 rb + li, as float q mod 4;
+//   A (FP16, FP8 form): STEPS pieces of 64 lanes x 8 halves; lane
+//      li + 16 (q / 8) of piece s holds row 16 rb + li, as half q mod 8.
 template <class T>
 __device__ __forceinline__ long long mix_frag_b(int r, int k, int nch) {
   constexpr int KC = MixK<T>::KC, EPL = 16 / (int)sizeof(typename Mix<T>::E);
@@ -128,16 +146,20 @@ __device__ __forceinline__ long long mix_frag_b(int r, int k, int nch) {
 }
 template <class T>
 __device__ __forceinline__ long long mix_frag_a(int r, int k, int nch) {
-  constexpr int KC = MixK<T>::KC, AP = 2 * MixK<T>::STEPS;
+  constexpr int KC = MixK<T>::KC, AP = MixA<T>::AP;
   const int rb = r >> 4, li = r & 15, c = k / KC, kk = k % KC, st = kk >> 5, q = kk & 31;
-  return ((((long long)rb * nch + c) * AP + 2 * st + ((q >> 2) & 1)) * 64 + li + 16 * (q >> 3)) * 4 +
-         (q & 3);
+  if constexpr (sizeof(typename MixA<T>::E) == 2)
+    return ((((long long)rb * nch + c) * AP + st) * 64 + li + 16 * (q >> 3)) * 8 + (q & 7);
+  else
+    return ((((long long)rb * nch + c) * AP + 2 * st + ((q >> 2) & 1)) * 64 + li + 16 * (q >> 3)) * 4 +
+           (q & 3);
 }
 
 template <class T>
 __global__ void mixed_prep_kernel(const double *__restrict__ Lp, int n_aux_pad, int rows_pad,
                                   int ldl, int ldlk, const float *__restrict__ colscale,
-                                  float *__restrict__ Lf, typename Mix<T>::E *__restrict__ Bhi,
+                                  typename MixA<T>::E *__restrict__ Lf,
+                                  typename Mix<T>::E *__restrict__ Bhi,
                                   typename Mix<T>::E *__restrict__ Blo) {
   const long long total = (long long)rows_pad * ldlk;
   const int nch = ldlk / MixK<T>::KC;
@@ -146,9 +168,13 @@ __global__ void mixed_prep_kernel(const double *__restrict__ Lp, int n_aux_pad, 
     const int r = (int)(idx / ldlk), k = (int)(idx % ldlk);
     const bool in = r < n_aux_pad && k < ldl;
     const double v = in ? Lp[(long long)r * ldl + k] : 0.0;
-    Lf[mix_frag_a<T>(r, k, nch)] = (float)v;
+    const double vs = colscale && in ? v * (double)colscale[k] : v;
+    if constexpr (sizeof(typename MixA<T>::E) == 2)
+      Lf[mix_frag_a<T>(r, k, nch)] = (typename MixA<T>::E)(float)vs;  // the scaled value
+    else
+      Lf[mix_frag_a<T>(r, k, nch)] = (float)v;
     typename Mix<T>::E h, l;
-    Mix<T>::split((float)(colscale && in ? v * (double)colscale[k] : v), h, l);
+    Mix<T>::split((float)vs, h, l);
     const long long ib = mix_frag_b<T>(r, k, nch);
     Bhi[ib] = h;
     Blo[ib] = l;
@@ -207,13 +233,16 @@ __global__ void taskscale_kernel(const double *__restrict__ chi_re, const double
 // Per-frequency FP32 chi with the column scales 2^-e_k and the frequency scale
 // 2^g folded in (the same float operations as the A operand needs), per K
 // chunk of 32 the 32 Re values then the 32 Im values: cf[f][k / 32][2][32].
+// With an A source that already carries 2^e_k (FP8), the column factor is
+// 2^-2 e_k, so that A = L chi 2^-e_k 2^g either way.
 __global__ void __launch_bounds__(256)
 mixed_chi_kernel(const double *__restrict__ chi_re, const double *__restrict__ chi_im, int ldl,
-                 const float *__restrict__ inv_colscale, const float *__restrict__ tscale,
-                 float *__restrict__ cf) {
+                 const float *__restrict__ inv_colscale, int scaled_source,
+                 const float *__restrict__ tscale, float *__restrict__ cf) {
   const int k = blockIdx.x * 256 + threadIdx.x, f = blockIdx.y;
   if (k >= ldl) return;
-  const float s = inv_colscale ? inv_colscale[k] : 1.0f;
+  float s = inv_colscale ? inv_colscale[k] : 1.0f;
+  if (scaled_source) s *= s;
   const float g = tscale ? tscale[f] : 1.0f;
   float *o = cf + (long long)f * 2 * ldl + (k / MX_KSTEP) * 2 * MX_KSTEP + k % MX_KSTEP;
   o[0] = (float)chi_re[(long long)f * ldl + k] * s * g;
@@ -235,10 +264,15 @@ mixed_chi_kernel(const double *__restrict__ chi_re, const double *__restrict__ c
 // the hardware returns zeros past the size instead of faulting.
 constexpr int BUF_FORMAT_WORD = 0x00020000;
 
-// The A rows of one chunk for one lane: 8 floats per MFMA K step.
+// The A rows of one chunk for one lane: 8 values per MFMA K step (FP32, or
+// FP16 for the FP8 form).
 template <class T>
 struct MixAReg {
   f8v v[MixK<T>::STEPS];
+};
+template <>
+struct MixAReg<e4m3> {
+  h8 v[MixK<e4m3>::STEPS];
 };
 
 // The loads of one K chunk (columns kc .. kc + KC), issued in three parts
@@ -250,8 +284,9 @@ struct MixAReg {
 template <class T>
 struct MixFetch {
   using E = typename Mix<T>::E;
-  static constexpr int KC = MixK<T>::KC, AP = 2 * MixK<T>::STEPS;
+  static constexpr int KC = MixK<T>::KC, AP = MixA<T>::AP;
   static constexpr int LOADS = 1 + AP + 4;  // loads of one fetch per wave
+  static constexpr int A_CHUNK = AP * 1024 / KC;  // A bytes per K column of a 16-row block
   __amdgpu_buffer_rsrc_t rA, rBh, rBl, rC;
   int voA[AP], voB[2], wave, lane;
 
@@ -264,11 +299,15 @@ struct MixFetch {
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rC, C, 16, 16 * lane + kc * 8, 0, 0, 0);
 #pragma unroll
     for (int st = 0; st < MixK<T>::STEPS; ++st) {
-      const f4v a0 = __builtin_bit_cast(
-          f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[2 * st] + kc * 64, 0, 0));
-      const f4v a1 = __builtin_bit_cast(
-          f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[2 * st + 1] + kc * 64, 0, 0));
-      areg.v[st] = f8v{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+      if constexpr (sizeof(typename MixA<T>::E) == 2) {
+        areg.v[st] = __builtin_bit_cast(h8, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[st] + kc * A_CHUNK, 0, 0));
+      } else {
+        const f4v a0 = __builtin_bit_cast(
+            f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[2 * st] + kc * A_CHUNK, 0, 0));
+        const f4v a1 = __builtin_bit_cast(
+            f4v, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[2 * st + 1] + kc * A_CHUNK, 0, 0));
+        areg.v[st] = f8v{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+      }
     }
   }
   // parts 1 and 2: the wave's B pieces 2 wave + j (hi and lo) into the stage
@@ -480,10 +519,11 @@ __device__ __forceinline__ void mix_multiply_pair(
   uc8 rh[4], rl[4], ih[4], il[4];  // [chunk a step 0, a 1, b 0, b 1]
 #pragma unroll
   for (int st = 0; st < 2; ++st) {
-    split8<e4m3>(la.v[st] * ld8(C_a + 64 * st + 8 * lq), rh[st], rl[st]);
-    split8<e4m3>(la.v[st] * ld8(C_a + 64 * st + 32 + 8 * lq), ih[st], il[st]);
-    split8<e4m3>(lb.v[st] * ld8(C_b + 64 * st + 8 * lq), rh[2 + st], rl[2 + st]);
-    split8<e4m3>(lb.v[st] * ld8(C_b + 64 * st + 32 + 8 * lq), ih[2 + st], il[2 + st]);
+    const f8v xa = __builtin_convertvector(la.v[st], f8v), xb = __builtin_convertvector(lb.v[st], f8v);
+    split8<e4m3>(xa * ld8(C_a + 64 * st + 8 * lq), rh[st], rl[st]);
+    split8<e4m3>(xa * ld8(C_a + 64 * st + 32 + 8 * lq), ih[st], il[st]);
+    split8<e4m3>(xb * ld8(C_b + 64 * st + 8 * lq), rh[2 + st], rl[2 + st]);
+    split8<e4m3>(xb * ld8(C_b + 64 * st + 32 + 8 * lq), ih[2 + st], il[2 + st]);
   }
   const i8v AH = mix_cat(rh[0], rh[1], rh[2], rh[3]), AL = mix_cat(rl[0], rl[1], rl[2], rl[3]);
   const i8v IH = mix_cat(ih[0], ih[1], ih[2], ih[3]), IL = mix_cat(il[0], il[1], il[2], il[3]);
@@ -540,13 +580,14 @@ __device__ __forceinline__ bool mx_item(int wg, int n_tiles, int F, int group, i
 
 template <class T>
 __global__ void __launch_bounds__(512, 1)
-pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>::E *__restrict__ Bhi,
+pi_build_mixed_async_kernel(const typename MixA<T>::E *__restrict__ Lf,
+                            const typename Mix<T>::E *__restrict__ Bhi,
                             const typename Mix<T>::E *__restrict__ Blo, int ldl, int n_aux,
                             const float *__restrict__ cf_all, const float *__restrict__ tscale,
                             const int2 *__restrict__ tiles, int n_tiles, int F, int group,
                             double2 *__restrict__ G, long long g_stride, int ldg) {
   using E = typename Mix<T>::E;
-  constexpr int KC = MixK<T>::KC, AP = 2 * MixK<T>::STEPS;
+  constexpr int KC = MixK<T>::KC, AP = MixA<T>::AP;
   // three stages as separate objects (the compiler then needs no wait between
   // a fetch into one and the reads of another); a stage's B pieces are 16 KB
   // of each split part in every form
@@ -583,7 +624,8 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
   const int nch = (ldl + KPAD - 1) / KPAD * (KPAD / KC);  // the operands span nch KC columns
   constexpr int PIECE = 1024 / (int)sizeof(E);
   const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
-      (void *)(Lf + (long long)(P0 / 16) * nch * AP * 256), 0, 8 * nch * AP * 1024, BUF_FORMAT_WORD);
+      (void *)(reinterpret_cast<const char *>(Lf) + (long long)(P0 / 16) * nch * AP * 1024), 0,
+      8 * nch * AP * 1024, BUF_FORMAT_WORD);
   const __amdgpu_buffer_rsrc_t rBh = __builtin_amdgcn_make_buffer_rsrc(
       (void *)(Bhi + (long long)(Q0 / 16) * nch * PIECE), 0, 16 * nch * 1024, BUF_FORMAT_WORD);
   const __amdgpu_buffer_rsrc_t rBl = __builtin_amdgcn_make_buffer_rsrc(
@@ -668,7 +710,7 @@ pi_build_mixed_async_kernel(const float *__restrict__ Lf, const typename Mix<T>:
 
 // ---------------------------------------------------------------------------
 void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, int ldl, int ldlk,
-                       float *Lf, void *Bhi, void *Blo, float *colscale, float *inv_colscale,
+                       void *Lf, void *Bhi, void *Blo, float *colscale, float *inv_colscale,
                        float *acol, hipStream_t stream) {
   long long blocks = ((long long)rows_pad * ldlk + 255) / 256;
   if (blocks > 65536) blocks = 65536;
@@ -676,22 +718,22 @@ void launch_mixed_prep(int prec, const double *Lp, int n_aux_pad, int rows_pad, 
     colscale_kernel<<<(ldl + 255) / 256, 256, 0, stream>>>(Lp, n_aux_pad, ldl, Mix<_Float16>::TARGET,
                                                             colscale, inv_colscale, acol);
     mixed_prep_kernel<_Float16><<<(unsigned)blocks, 256, 0, stream>>>(
-        Lp, n_aux_pad, rows_pad, ldl, ldlk, colscale, Lf, static_cast<unsigned short *>(Bhi),
-        static_cast<unsigned short *>(Blo));
+        Lp, n_aux_pad, rows_pad, ldl, ldlk, colscale, static_cast<float *>(Lf),
+        static_cast<unsigned short *>(Bhi), static_cast<unsigned short *>(Blo));
   } else if (prec == 3) {
     colscale_kernel<<<(ldl + 255) / 256, 256, 0, stream>>>(Lp, n_aux_pad, ldl, Mix<e4m3>::TARGET,
                                                             colscale, inv_colscale, acol);
     mixed_prep_kernel<e4m3><<<(unsigned)blocks, 256, 0, stream>>>(
-        Lp, n_aux_pad, rows_pad, ldl, ldlk, colscale, Lf, static_cast<unsigned char *>(Bhi),
-        static_cast<unsigned char *>(Blo));
+        Lp, n_aux_pad, rows_pad, ldl, ldlk, colscale, static_cast<_Float16 *>(Lf),
+        static_cast<unsigned char *>(Bhi), static_cast<unsigned char *>(Blo));
   } else {
     mixed_prep_kernel<__bf16><<<(unsigned)blocks, 256, 0, stream>>>(
-        Lp, n_aux_pad, rows_pad, ldl, ldlk, nullptr, Lf, static_cast<unsigned short *>(Bhi),
-        static_cast<unsigned short *>(Blo));
+        Lp, n_aux_pad, rows_pad, ldl, ldlk, nullptr, static_cast<float *>(Lf),
+        static_cast<unsigned short *>(Bhi), static_cast<unsigned short *>(Blo));
   }
 }
 
-void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const void *Blo, int ldl,
+void launch_pi_build_mixed(int prec, const void *Lf, const void *Bhi, const void *Blo, int ldl,
                            int n_aux, const double *chi_re, const double *chi_im,
                            const float *inv_colscale, const float *acol, float *tscale, float *chi_f32,
                            int F, const int2 *tiles, int n_tiles, double2 *G, long long g_stride,
@@ -704,22 +746,23 @@ void launch_pi_build_mixed(int prec, const float *Lf, const void *Bhi, const voi
                                             prec == 3 ? Mix<e4m3>::TARGET : Mix<_Float16>::TARGET, acol,
                                             tscale);
   mixed_chi_kernel<<<dim3((ldl + 255) / 256, F), 256, 0, stream>>>(
-      chi_re, chi_im, ldl, scaled ? inv_colscale : nullptr, scaled ? tscale : nullptr, chi_f32);
+      chi_re, chi_im, ldl, scaled ? inv_colscale : nullptr, prec == 3, scaled ? tscale : nullptr,
+      chi_f32);
   // (tile, frequency-group) blocks, rounded up to a whole turn of the XCDs
   const int group = F < 32 ? F : 32;
   const long long blocks = (long long)n_tiles * ((F + group - 1) / group);
   const long long wgs = (blocks + MX_NXCD - 1) / MX_NXCD * MX_NXCD * group;
   if (prec == 3)
     pi_build_mixed_async_kernel<e4m3><<<(unsigned)wgs, 512, 0, stream>>>(
-        Lf, static_cast<const unsigned char *>(Bhi), static_cast<const unsigned char *>(Blo), ldl,
+        static_cast<const _Float16 *>(Lf), static_cast<const unsigned char *>(Bhi), static_cast<const unsigned char *>(Blo), ldl,
         n_aux, chi_f32, tscale, tiles, n_tiles, F, group, G, g_stride, ldg);
   else if (prec == 2)
     pi_build_mixed_async_kernel<_Float16><<<(unsigned)wgs, 512, 0, stream>>>(
-        Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
+        static_cast<const float *>(Lf), static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
         n_aux, chi_f32, tscale, tiles, n_tiles, F, group, G, g_stride, ldg);
   else
     pi_build_mixed_async_kernel<__bf16><<<(unsigned)wgs, 512, 0, stream>>>(
-        Lf, static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
+        static_cast<const float *>(Lf), static_cast<const unsigned short *>(Bhi), static_cast<const unsigned short *>(Blo), ldl,
         n_aux, chi_f32, nullptr, tiles, n_tiles, F, group, G, g_stride, ldg);
 }
 
