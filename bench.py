@@ -132,6 +132,20 @@ def cpu_baseline_child(args):
             break
     t_task = (time.perf_counter() - t0) / done
 
+    # the same residue tasks on one thread (the first few of the sample)
+    t_task1, done1 = None, 0
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            for k in order[:3]:
+                m, z = tasks[k]
+                OS.screened_element(L, d, OS.pair_vector(s.M_oo, s.M_ov, n, m), z)
+                done1 += 1
+            t_task1 = (time.perf_counter() - t0) / done1
+    except ImportError:
+        pass
+
     t0 = time.perf_counter()
     for w in grid:
         OS.imag_integral(W, s.eps, s.omega_imag, s.w_imag, w)
@@ -158,6 +172,12 @@ def cpu_baseline_child(args):
                    f"task count to {t_solve:.0f} s per solve"),
         "sampled_s": t_imag + done * t_task + t_quad + t_cum,
         "cpu_model": _cpu_model(),
+        # one thread: the residue tasks timed on one thread, the imaginary axis
+        # scaled by the same ratio (both are dense FP64 factorisations)
+        "single_thread": None if t_task1 is None else {
+            "value": 1.0 / ((t_imag + len(tasks) * t_task) * t_task1 / t_task + t_quad + t_cum),
+            "unit": "solves/s", "task_ms": t_task1 * 1e3, "tasks_timed": done1,
+            "note": "residue part and imaginary axis scaled by the one-thread task time"},
     }), flush=True)
 
 

@@ -379,7 +379,7 @@ __device__ __forceinline__ void split8<__bf16>(f8v x, us8 &hi, us8 &lo) {
   lo = __builtin_bit_cast(us8, __builtin_convertvector(x - hf, t8));
 }
 // e4m3: pairs converted into the halves of a word (round to nearest even, the
-// same conversions as Mix<e4m3>::split), hi read back per byte
+// same conversions as Mix<e4m3>::split), hi read back per pair
 template <>
 __device__ __forceinline__ void split8<e4m3>(f8v x, uc8 &hi, uc8 &lo) {
   typedef int i2 __attribute__((ext_vector_type(2)));
@@ -387,10 +387,11 @@ __device__ __forceinline__ void split8<e4m3>(f8v x, uc8 &hi, uc8 &lo) {
   h0 = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], h0, true);
   int h1 = __builtin_amdgcn_cvt_pk_fp8_f32(x[4], x[5], 0, false);
   h1 = __builtin_amdgcn_cvt_pk_fp8_f32(x[6], x[7], h1, true);
-  const f8v hf = f8v{__builtin_amdgcn_cvt_f32_fp8(h0, 0), __builtin_amdgcn_cvt_f32_fp8(h0, 1),
-                     __builtin_amdgcn_cvt_f32_fp8(h0, 2), __builtin_amdgcn_cvt_f32_fp8(h0, 3),
-                     __builtin_amdgcn_cvt_f32_fp8(h1, 0), __builtin_amdgcn_cvt_f32_fp8(h1, 1),
-                     __builtin_amdgcn_cvt_f32_fp8(h1, 2), __builtin_amdgcn_cvt_f32_fp8(h1, 3)};
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  // hi back in FP32 two values per conversion (the low, then the high word)
+  const f2 p0 = __builtin_amdgcn_cvt_pk_f32_fp8(h0, false), p1 = __builtin_amdgcn_cvt_pk_f32_fp8(h0, true);
+  const f2 p2 = __builtin_amdgcn_cvt_pk_f32_fp8(h1, false), p3 = __builtin_amdgcn_cvt_pk_f32_fp8(h1, true);
+  const f8v hf = f8v{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
   const f8v r = x - hf;
   int l0 = __builtin_amdgcn_cvt_pk_fp8_f32(r[0], r[1], 0, false);
   l0 = __builtin_amdgcn_cvt_pk_fp8_f32(r[2], r[3], l0, true);
