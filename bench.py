@@ -238,9 +238,11 @@ def measure_peaks(gwc):
         "fp64_mfma_tflops": gwc.probe_peak("fp64_mfma"),
         "bf16_mfma_tflops": gwc.probe_peak("bf16_mfma"),
         "fp16_mfma_tflops": gwc.probe_peak("fp16_mfma"),
+        "fp8_k32_mfma_tflops": gwc.probe_peak("fp8_mfma_k32"),
+        "fp8_k128_mfma_tflops": gwc.probe_peak("fp8_mfma_k128"),
         "hbm_copy_gbs": gwc.probe_peak("hbm_copy"),
         "datasheet": {"fp64_mfma_tflops": 78.6, "bf16_mfma_tflops": 2500.0,
-                      "fp16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0},
+                      "fp16_mfma_tflops": 2500.0, "fp8_mfma_tflops": 5000.0, "hbm_gbs": 8000.0},
     }
 
 

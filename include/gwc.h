@@ -465,6 +465,9 @@ int gwc_timing_get(const char *kernel, double *total_ms, long long *launches, do
  *   kind 1  BF16 MFMA (v_mfma_f32_16x16x32_bf16), TFLOP/s
  *   kind 2  FP16 MFMA (v_mfma_f32_16x16x32_f16), TFLOP/s
  *   kind 3  device-memory copy of 4 GiB, GB/s counting bytes read + written
+ *   kind 4  FP8 MFMA, K = 32 (v_mfma_f32_16x16x32_fp8_fp8, E4M3), TFLOP/s
+ *   kind 5  FP8 MFMA, K = 128 (v_mfma_f32_16x16x128_f8f6f4, E4M3, no block
+ *           scales), TFLOP/s
  * The MFMA probes keep operands in registers (independent accumulator chains,
  * no memory traffic in the loop); each figure is the median of five timed
  * launches after one untimed launch.  Allocates temporaries (2 x 4 GiB for

@@ -276,7 +276,8 @@ def timing_get(kernel: str) -> dict:
     return {"total_ms": ms.value, "launches": n.value, "flops": fl.value}
 
 
-PROBE_KINDS = {"fp64_mfma": 0, "bf16_mfma": 1, "fp16_mfma": 2, "hbm_copy": 3}
+PROBE_KINDS = {"fp64_mfma": 0, "bf16_mfma": 1, "fp16_mfma": 2, "hbm_copy": 3, "fp8_mfma_k32": 4,
+               "fp8_mfma_k128": 5}
 
 
 def probe_peak(kind: str) -> float:

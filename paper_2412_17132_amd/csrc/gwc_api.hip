@@ -1500,7 +1500,7 @@ const char *gwc_last_error(void) { return gwc::last_error().c_str(); }
 
 int gwc_probe_peak(int kind, double *value, void *hip_stream) {
   return guarded([&] {
-    if (!value || kind < 0 || kind > 3) fail(GWC_ERR_INVALID_ARG, "gwc_probe_peak: kind must be 0..3 and value non-NULL");
+    if (!value || kind < 0 || kind > 5) fail(GWC_ERR_INVALID_ARG, "gwc_probe_peak: kind must be 0..5 and value non-NULL");
     HIPCHECK(gwc::probe_peak(kind, (hipStream_t)hip_stream, value));
     return GWC_OK;
   });

@@ -77,6 +77,43 @@ probe_mfma16_kernel(int iters, float seed, float *__restrict__ out) {
   out[(size_t)blockIdx.x * PROBE_THREADS + threadIdx.x] = s;
 }
 
+// FP8 (E4M3) MFMA: K = 32 (v_mfma_f32_16x16x32_fp8_fp8, 8 bytes per lane and
+// operand) or K = 128 (v_mfma_f32_16x16x128_f8f6f4 without block scales, 32
+// bytes per lane and operand).  The operand bytes are small normal E4M3
+// values (no NaN codes).
+typedef int pi8 __attribute__((ext_vector_type(8)));
+template <int K>
+__global__ void __launch_bounds__(PROBE_THREADS)
+probe_mfma_fp8_kernel(int iters, int seed, float *__restrict__ out) {
+  pi8 a, b;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    a[e] = (seed + (int)threadIdx.x + e) & 0x37373737;
+    b[e] = (seed + 3 * (int)threadIdx.x + e) & 0x37373737;
+  }
+  pf4 acc[PROBE_CHAINS];
+#pragma unroll
+  for (int c = 0; c < PROBE_CHAINS; ++c) acc[c] = pf4{0.f, 0.f, 0.f, 0.f};
+  for (int it = 0; it < iters; it += 32) {
+#pragma unroll
+    for (int u = 0; u < 32; ++u)
+#pragma unroll
+      for (int c = 0; c < PROBE_CHAINS; ++c) {
+        if constexpr (K == 128) {
+          acc[c] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[c], 0, 0, 0, 0, 0, 0);
+        } else {
+          const long a2 = ((long)(unsigned)a[1] << 32) | (unsigned)a[0];
+          const long b2 = ((long)(unsigned)b[1] << 32) | (unsigned)b[0];
+          acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a2, b2, acc[c], 0, 0, 0);
+        }
+      }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < PROBE_CHAINS; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  out[(size_t)blockIdx.x * PROBE_THREADS + threadIdx.x] = s;
+}
+
 // Four independent 16-byte loads in flight per thread and iteration; n is a
 // multiple of 4 * gridDim.x * PROBE_THREADS (the host sizes it so).
 __global__ void __launch_bounds__(PROBE_THREADS)
@@ -127,14 +164,15 @@ double time_launches(hipStream_t s, int reps, Launch &&launch) {
 }  // namespace
 
 // kind 0: FP64 MFMA TFLOP/s; 1: BF16 MFMA TFLOP/s; 2: FP16 MFMA TFLOP/s;
-// 3: HBM copy GB/s (bytes read + written).  Returns hipSuccess or the error.
+// 3: HBM copy GB/s (bytes read + written); 4: FP8 MFMA K = 32 TFLOP/s;
+// 5: FP8 MFMA K = 128 TFLOP/s.  Returns hipSuccess or the error.
 hipError_t probe_peak(int kind, hipStream_t s, double *value) {
   try {
     int dev = 0, n_cu = 0;
     PROBECHECK(hipGetDevice(&dev));
     PROBECHECK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     const int blocks = n_cu * 8;
-    if (kind <= 2) {
+    if (kind <= 2 || kind == 4 || kind == 5) {
       const int iters = 16384;  // 10-20 ms per launch at the datasheet rates
       void *out = nullptr;
       PROBECHECK(hipMallocAsync(&out, (size_t)blocks * PROBE_THREADS * sizeof(double), s));
@@ -147,14 +185,22 @@ hipError_t probe_peak(int kind, hipStream_t s, double *value) {
         ms = time_launches(s, 5, [&] {
           probe_mfma16_kernel<__bf16, pbf8><<<blocks, PROBE_THREADS, 0, s>>>(iters, 0.5f, (float *)out);
         });
-      } else {
+      } else if (kind == 2) {
         ms = time_launches(s, 5, [&] {
           probe_mfma16_kernel<_Float16, ph8><<<blocks, PROBE_THREADS, 0, s>>>(iters, 0.5f, (float *)out);
+        });
+      } else if (kind == 4) {
+        ms = time_launches(s, 5, [&] {
+          probe_mfma_fp8_kernel<32><<<blocks, PROBE_THREADS, 0, s>>>(iters, 0x01020304, (float *)out);
+        });
+      } else {
+        ms = time_launches(s, 5, [&] {
+          probe_mfma_fp8_kernel<128><<<blocks, PROBE_THREADS, 0, s>>>(iters, 0x01020304, (float *)out);
         });
       }
       PROBECHECK(hipFreeAsync(out, s));
       PROBECHECK(hipStreamSynchronize(s));
-      const double per_mfma = kind == 0 ? 2.0 * 16 * 16 * 4 : 2.0 * 16 * 16 * 32;
+      const double per_mfma = kind == 0 ? 2.0 * 16 * 16 * 4 : kind == 5 ? 2.0 * 16 * 16 * 128 : 2.0 * 16 * 16 * 32;
       const double waves = (double)blocks * (PROBE_THREADS / 64);
       *value = waves * iters * PROBE_CHAINS * per_mfma / (ms * 1e-3) / 1e12;
       return hipSuccess;
