@@ -238,7 +238,7 @@ int gwc_spectral_cumulant(const gwc_cumulant_args *args, double *A_out, double *
  * allocate (code under stream capture, serving loops that forbid hipMalloc):
  * the same arguments, kernels, results and errors, with every temporary in one
  * library-owned device array per GPU (about 21 MB, held until the process
- * ends) instead of the stream-ordered pool.  Limits: n_t <= 2^19 and
+ * ends) instead of the library's cache of device blocks.  Limits: n_t <= 2^19 and
  * n_real <= 2^15; larger sizes return GWC_ERR_SHAPE.  Inputs and outputs may
  * be host or device memory, as for gwc_spectral_cumulant.  All calls on one GPU
  * share that array: calls that overlap on one GPU (several host threads or

@@ -104,43 +104,165 @@ void timing_resolve(std::vector<PendingTiming> &pending) {
 }
 
 // ---------------------------------------------------------------------------
-// Stream-ordered temporary allocation (freed in stream order at scope exit).
-void configure_pool_once() {
-  static std::once_flag once;
-  std::call_once(once, [] {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return; }
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-      uint64_t thr = UINT64_MAX;
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    (void)hipGetLastError();
-  });
+// Temporary device memory: a cache of device blocks by size class.
+//
+// A stream-ordered pool (hipMallocAsync) maps new memory whenever none of its
+// freed blocks may go to the asking stream, and such a growth by several GB
+// held every stream of the device for up to seconds: serving workers on
+// their own streams, whose batch buffers reach a quarter of the HBM budget,
+// met it on many requests.  Here a freed block waits in its size class with
+// an event recorded on the freeing stream; it goes out again at once to the
+// same stream (stream order covers it) and to another stream once the event
+// has completed.  Only a miss allocates (hipMalloc).  Idle blocks are kept
+// up to half the device's memory (beyond that the oldest are freed), and an
+// allocation that fails first frees every idle block and tries again.
+// Classes: powers of two up to 1 MiB, above that multiples of 1/32 of the
+// next power of two (at most about 6 % of a block unused).
+size_t cache_class(size_t bytes) {
+  if (bytes <= 256) return 256;
+  size_t p = 1;
+  while (p < bytes) p <<= 1;
+  if (p <= ((size_t)1 << 20)) return p;
+  const size_t q = p >> 5;
+  return (bytes + q - 1) / q * q;
 }
 
+class DeviceCache {
+ public:
+  // A block of `cls` bytes for use on stream s, or nullptr when the device
+  // has none to give.
+  void *get(size_t cls, hipStream_t s) {
+    {
+      // a pending event's query leaves hipErrorNotReady as the thread's last
+      // error: cleared unless an earlier error is waiting to be reported
+      const bool clean = hipPeekAtLastError() == hipSuccess;
+      std::lock_guard<std::mutex> lock(mu_);
+      for (size_t i = idle_.size(); i-- > 0;) {
+        Block &b = idle_[i];
+        if (b.cls != cls) continue;
+        bool ready = b.s == s || !b.ev;
+        if (!ready) {
+          ready = hipEventQuery(b.ev) == hipSuccess;
+          if (clean) (void)hipGetLastError();
+        }
+        if (!ready) continue;
+        void *p = b.p;
+        if (b.ev) (void)hipEventDestroy(b.ev);
+        idle_bytes_ -= b.cls;
+        idle_.erase(idle_.begin() + (long)i);
+        return p;
+      }
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, cls) != hipSuccess) {
+      (void)hipGetLastError();
+      trim(0);
+      p = nullptr;
+      if (hipMalloc(&p, cls) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    return p;
+  }
+  // Takes back a block last used on stream s.
+  void put(void *p, size_t cls, hipStream_t s) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, s) != hipSuccess) {
+      (void)hipGetLastError();
+      if (ev) (void)hipEventDestroy(ev);
+      ev = nullptr;
+      (void)hipStreamSynchronize(s);  // no event: the block is idle once the stream is
+      (void)hipGetLastError();
+    }
+    size_t over = 0;
+    {
+      std::lock_guard<std::mutex> lock(mu_);
+      idle_.push_back(Block{p, cls, s, ev});
+      idle_bytes_ += cls;
+      if (idle_bytes_ > cap()) over = idle_bytes_ - cap();
+    }
+    if (over) trim(cap());
+  }
+
+ private:
+  struct Block {
+    void *p;
+    size_t cls;
+    hipStream_t s;
+    hipEvent_t ev;
+  };
+  size_t cap() {
+    if (!cap_) {
+      size_t free_b = 0, total = 0;
+      if (hipMemGetInfo(&free_b, &total) != hipSuccess) {
+        (void)hipGetLastError();
+        total = (size_t)64 << 30;
+      }
+      cap_ = total / 2;
+    }
+    return cap_;
+  }
+  // Frees idle blocks, oldest first, until at most `keep` bytes stay idle.
+  void trim(size_t keep) {
+    std::vector<Block> out;
+    {
+      std::lock_guard<std::mutex> lock(mu_);
+      size_t k = 0;
+      while (k < idle_.size() && idle_bytes_ > keep) {
+        idle_bytes_ -= idle_[k].cls;
+        out.push_back(idle_[k]);
+        ++k;
+      }
+      idle_.erase(idle_.begin(), idle_.begin() + (long)k);
+    }
+    for (Block &b : out) {
+      if (b.ev) {
+        (void)hipEventSynchronize(b.ev);
+        (void)hipEventDestroy(b.ev);
+      }
+      (void)hipFree(b.p);
+    }
+    (void)hipGetLastError();
+  }
+  std::mutex mu_;
+  std::vector<Block> idle_;  // oldest first
+  size_t idle_bytes_ = 0, cap_ = 0;
+};
+
+constexpr int CACHE_DEVICES = 16;
+DeviceCache &device_cache() {
+  static DeviceCache caches[CACHE_DEVICES];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  return caches[dev >= 0 && dev < CACHE_DEVICES ? dev : 0];
+}
+
+// A temporary of one call, used on stream s and returned to the cache at
+// scope exit (in stream order).
 struct DevBuf {
   void *p = nullptr;
+  size_t cls = 0;
   hipStream_t s = nullptr;
+  DeviceCache *cache = nullptr;
   explicit DevBuf(hipStream_t stream) : s(stream) {}
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFreeAsync(p, s);
+    if (p) cache->put(p, cls, s);
     p = nullptr;
   }
   void alloc(size_t bytes) {
     release();
-    configure_pool_once();
     if (bytes == 0) bytes = 16;
-    hipError_t e = hipMallocAsync(&p, bytes, s);
-    if (e != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      fail(e == hipErrorOutOfMemory ? GWC_ERR_OUT_OF_MEMORY : GWC_ERR_DEVICE,
-           "allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
-    }
+    cache = &device_cache();
+    cls = cache_class(bytes);
+    p = cache->get(cls, s);
+    if (!p) fail(GWC_ERR_OUT_OF_MEMORY, "allocation of %zu bytes failed", bytes);
   }
   template <class T>
   T *as() const {
