@@ -71,15 +71,21 @@ __device__ __forceinline__ bool xcd_item(int wg, int items, int F, int &f, int &
 
 // D: one workgroup (256 threads) per matrix.  X = the lower triangle of the
 // kb x kb diagonal block (identity beyond kb).  Step t: every row i > t takes
-// X[i][j] -= (X[i][t] / d_t) X[j][t] for t < j <= i, then column t is scaled
-// by 1/d_t.  Thread tid owns row tid / 4 and the columns j = tid % 4 (mod 4).
-// Afterwards X holds L11 (unit, strictly lower) and D1 (diagonal); D1^-1 goes
-// to dinv_g[f N + K0 + t] and L11^-1 (the LU's right-looking in-place
-// inversion) to the scratch, zero-padded beyond kb.
+// X[i][j] -= (X[i][t] / d_t) X[j][t] for t < j <= i; the columns are scaled
+// by 1/d_t after the last step (a step reads column t and writes only the
+// columns right of it, so one barrier per step suffices).  Thread tid owns
+// row tid / 4 and the columns j = tid % 4 (mod 4); the four threads of a row
+// are in one wave.  Afterwards X holds L11 (unit, strictly lower) and D1
+// (diagonal); D1^-1 goes to dinv_g[f N + K0 + t] and L11^-1 (the LU's
+// right-looking in-place inversion, one barrier per step as well: step t
+// reads row t and writes only rows below it, and a row's multiplier is read
+// by the row's own wave before one of its threads overwrites it) to the
+// scratch, zero-padded beyond kb.
 __global__ void __launch_bounds__(256)
 ldlt_diag_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, int K0,
                  double2 *__restrict__ linv_g, double2 *__restrict__ dinv_g, int *__restrict__ status) {
   __shared__ double2 X[NB][NB + 1];
+  __shared__ double2 Dinv[NB];
   __shared__ int zero;
   const int f = blockIdx.x, tid = threadIdx.x;
   const double2 *A = G + (long long)f * gs;
@@ -96,30 +102,28 @@ ldlt_diag_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, in
     const double2 d = X[t][t];
     const bool dz = d.x == 0.0 && d.y == 0.0;
     const double2 inv = dz ? make_double2(0.0, 0.0) : zinv(d);
-    if (dz && tid == 0) zero = 1;
-    const double2 l = zmul(X[i][t], inv);
+    if (tid == 0) {
+      if (dz) zero = 1;
+      Dinv[t] = inv;
+    }
     if (i > t) {
+      const double2 l = zmul(X[i][t], inv);
       int j = t + 1 + ((j0 - (t + 1)) & 3);
       for (; j <= i; j += 4) X[i][j] = zsub(X[i][j], zmul(l, X[j][t]));
     }
     __syncthreads();
-    if (i > t && (t & 3) == j0) X[i][t] = l;
-    __syncthreads();
   }
-  // D1^-1
-  if (tid < kb) {
-    const double2 d = X[tid][tid];
-    dinv_g[(long long)f * N + K0 + tid] = !(d.x == 0.0 && d.y == 0.0) ? zinv(d) : make_double2(0.0, 0.0);
-  }
+  // L11: column t scaled by 1/d_t (the multipliers the steps used); D1^-1
+  for (int t = j0; t < i && t < kb; t += 4) X[i][t] = zmul(X[i][t], Dinv[t]);
+  if (tid < kb) dinv_g[(long long)f * N + K0 + tid] = Dinv[tid];
   __syncthreads();
   if (tid < NB) X[tid][tid] = make_double2(1.0, 0.0);
   __syncthreads();
   // L11^-1 in place: at step t every row i > t takes X[i][j] -= L[i][t] X[t][j]
   // for j < t and X[i][t] = -L[i][t] (row t of X is final by then)
   for (int t = 0; t < NB - 1; ++t) {
-    const double2 l = X[i][t];
-    __syncthreads();
     if (i > t) {
+      const double2 l = X[i][t];
       for (int j = j0; j < t; j += 4) X[i][j] = zsub(X[i][j], zmul(l, X[t][j]));
       if ((t & 3) == j0) X[i][t] = make_double2(-l.x, -l.y);
     }
