@@ -165,6 +165,11 @@ class DeviceCache {
     }
     return p;
   }
+  // Bytes held idle (free for the library's next temporaries).
+  size_t idle_bytes() {
+    std::lock_guard<std::mutex> lock(mu_);
+    return idle_bytes_;
+  }
   // Takes back a block last used on stream s.
   void put(void *p, size_t cls, hipStream_t s) {
     hipEvent_t ev = nullptr;
@@ -352,7 +357,7 @@ size_t default_batch_bytes() {
   }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
-    budget = std::min(budget, free_b / 2);
+    budget = std::min(budget, (free_b + device_cache().idle_bytes()) / 2);  // idle cached blocks count as free
   else
     (void)hipGetLastError();
   return budget;
