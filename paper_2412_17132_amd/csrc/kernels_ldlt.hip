@@ -91,10 +91,24 @@ ldlt_diag_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, in
   const double2 *A = G + (long long)f * gs;
   const int kb = min(NB, N - K0);
   if (tid == 0) zero = 0;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int i = idx / NB, j = idx - i * NB;
-    X[i][j] = (i < kb && j <= i) ? A[(long long)(K0 + i) * ldg + K0 + j]
-                                 : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  {
+    // all of a thread's loads in flight before its first LDS store
+    constexpr int PER = NB * NB / 256;
+    double2 v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      // every load unconditional, from an element inside the block (a load
+      // under a branch would be waited for before the other branch's write)
+      const int idx = q * 256 + tid, i = idx / NB, j = idx - i * NB;
+      const int ic = min(i, kb - 1), jc = min(j, ic);
+      const double2 a = A[(long long)(K0 + ic) * ldg + K0 + jc];
+      v[q] = (i < kb && j <= i) ? a : make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = q * 256 + tid;
+      X[idx / NB][idx % NB] = v[q];
+    }
   }
   __syncthreads();
   const int i = tid >> 2, j0 = tid & 3;
@@ -130,8 +144,9 @@ ldlt_diag_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, in
     __syncthreads();
   }
   double2 *Li = linv_g + (long long)f * NB * NB;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx / NB, c = idx - r * NB;
+#pragma unroll
+  for (int q = 0; q < NB * NB / 256; ++q) {
+    const int idx = q * 256 + tid, r = idx / NB, c = idx - r * NB;
     Li[idx] = (r < kb && c < kb) ? X[r][c] : make_double2(0.0, 0.0);
   }
   if (tid == 0 && zero) status[f] = 1;
@@ -157,9 +172,18 @@ ldlt_trsm_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, i
   const int li = lane & 15, lk = lane >> 4;
   double2 *A = G + (long long)f * gs;
   const double2 *Li = linv_g + (long long)f * NB * NB;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx / NB, k = idx - r * NB;
-    S[r][k] = (r0 + r < n && k < kb) ? A[(long long)(r0 + r) * ldg + K0 + k] : make_double2(0.0, 0.0);
+  // all of a thread's loads in flight before its first LDS store
+  constexpr int PER = NB * NB / 256;
+  double2 v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = q * 256 + tid, r = idx / NB, k = idx - r * NB;
+    v[q] = (r0 + r < n && k < kb) ? A[(long long)(r0 + r) * ldg + K0 + k] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = q * 256 + tid;
+    S[idx / NB][idx % NB] = v[q];
   }
   __syncthreads();
   d4 re[4], im[4];
@@ -169,7 +193,10 @@ ldlt_trsm_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, i
     im[b] = d4{0.0, 0.0, 0.0, 0.0};
   }
   const int wr = 16 * wave;
-  for (int kk = 0; kk < kb; kk += 4) {
+  // the whole K of 64 unrolled (S and L11^-1 are zero beyond kb), so that the
+  // L11^-1 loads of later steps are issued ahead of the products
+#pragma unroll
+  for (int kk = 0; kk < NB; kk += 4) {
     const int k = kk + lk;
     // A operand: rows wr + li of the block, column k; B operand:
     // L11^-T [k][c] = L11^-1 [c][k] (zero for k >= kb), c = 16 b + li.
@@ -192,8 +219,9 @@ ldlt_trsm_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R, i
 #pragma unroll
     for (int r = 0; r < 4; ++r) S[wr + 4 * r + lk][16 * b + li] = make_double2(re[b][r], im[b][r]);
   __syncthreads();
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int k = idx / NB, r = idx - k * NB;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = q * 256 + tid, k = idx / NB, r = idx - k * NB;
     if (k < kb && r0 + r < n) A[(long long)(K0 + k) * ldg + r0 + r] = S[r][k];
   }
 }
