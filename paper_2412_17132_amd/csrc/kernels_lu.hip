@@ -658,26 +658,33 @@ lu_trailing_kernel(double2 *__restrict__ G, long long gs, int ldg, int N, int R,
     mfmas(lv, uv);
   }
 
-  // each 16 x 16 block: its four values per lane are all loaded before any is
-  // stored (one memory round trip per block)
+  // the tile's values, a row of 16 x 16 blocks at a time: the eight values per
+  // lane loaded before any is stored (two memory round trips for the tile;
+  // the compiler cannot move a block's loads above the stores of another, and
+  // all sixteen at once would not fit beside the accumulators)
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 2; ++a) {
+    double2 x[2][4];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const int col = ca + wc + 16 * b + li, colc = min(col, col_end - 1);
-      double2 x[4];
+      const int colc = min(ca + wc + 16 * b + li, col_end - 1);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        x[r] = A[(long long)min(ra + wr + 16 * a + 4 * r + lk, n - 1) * ldg + colc];
+        x[b][r] = A[(long long)min(ra + wr + 16 * a + 4 * r + lk, n - 1) * ldg + colc];
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = ca + wc + 16 * b + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = ra + wr + 16 * a + 4 * r + lk;
         const double q1 = p1[a][b][r], q2 = p2[a][b][r];
         if (row < n && col < col_end)
           A[(long long)row * ldg + col] =
-              make_double2(x[r].x - (q1 - q2), x[r].y - (p3[a][b][r] - q1 - q2));
+              make_double2(x[b][r].x - (q1 - q2), x[b][r].y - (p3[a][b][r] - q1 - q2));
       }
     }
+  }
 }
 
 // ===========================================================================
