@@ -70,7 +70,7 @@ __device__ __forceinline__ bool xcd_item(int wg, int items, int F, int &f, int &
 }
 
 // D: one workgroup (256 threads) per matrix.  X = the lower triangle of the
-// kb x kb diagonal block (identity beyond kb).  Step t: every row i > t takes
+// kb x kb diagonal block (identity beyond kb), stored packed in LDS.  Step t: every row i > t takes
 // X[i][j] -= (X[i][t] / d_t) X[j][t] for t < j <= i; the columns are scaled
 // by 1/d_t after the last step (a step reads column t and writes only the
 // columns right of it, so one barrier per step suffices).  Thread tid owns
@@ -84,9 +84,11 @@ __device__ __forceinline__ bool xcd_item(int wg, int items, int F, int &f, int &
 __global__ void __launch_bounds__(256)
 ldlt_diag_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, int K0,
                  double2 *__restrict__ linv_g, double2 *__restrict__ dinv_g, int *__restrict__ status) {
-  __shared__ double2 X[NB][NB + 1];
+  // the lower triangle only, row by row (33 KB: four workgroups per CU)
+  __shared__ double2 Xp[NB * (NB + 1) / 2];
   __shared__ double2 Dinv[NB];
   __shared__ int zero;
+  auto X = [&](int r, int c) -> double2 & { return Xp[(r * (r + 1) >> 1) + c]; };
   const int f = blockIdx.x, tid = threadIdx.x;
   const double2 *A = G + (long long)f * gs;
   const int kb = min(NB, N - K0);
@@ -106,14 +108,14 @@ ldlt_diag_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, in
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int idx = q * 256 + tid;
-      X[idx / NB][idx % NB] = v[q];
+      const int idx = q * 256 + tid, i = idx / NB, j = idx - i * NB;
+      if (j <= i) X(i, j) = v[q];
     }
   }
   __syncthreads();
   const int i = tid >> 2, j0 = tid & 3;
   for (int t = 0; t < kb; ++t) {
-    const double2 d = X[t][t];
+    const double2 d = X(t, t);
     const bool dz = d.x == 0.0 && d.y == 0.0;
     const double2 inv = dz ? make_double2(0.0, 0.0) : zinv(d);
     if (tid == 0) {
@@ -121,33 +123,34 @@ ldlt_diag_kernel(const double2 *__restrict__ G, long long gs, int ldg, int N, in
       Dinv[t] = inv;
     }
     if (i > t) {
-      const double2 l = zmul(X[i][t], inv);
+      const double2 l = zmul(X(i, t), inv);
       int j = t + 1 + ((j0 - (t + 1)) & 3);
-      for (; j <= i; j += 4) X[i][j] = zsub(X[i][j], zmul(l, X[j][t]));
+      for (; j <= i; j += 4) X(i, j) = zsub(X(i, j), zmul(l, X(j, t)));
     }
     __syncthreads();
   }
   // L11: column t scaled by 1/d_t (the multipliers the steps used); D1^-1
-  for (int t = j0; t < i && t < kb; t += 4) X[i][t] = zmul(X[i][t], Dinv[t]);
+  for (int t = j0; t < i && t < kb; t += 4) X(i, t) = zmul(X(i, t), Dinv[t]);
   if (tid < kb) dinv_g[(long long)f * N + K0 + tid] = Dinv[tid];
   __syncthreads();
-  if (tid < NB) X[tid][tid] = make_double2(1.0, 0.0);
+  if (tid < NB) X(tid, tid) = make_double2(1.0, 0.0);
   __syncthreads();
   // L11^-1 in place: at step t every row i > t takes X[i][j] -= L[i][t] X[t][j]
   // for j < t and X[i][t] = -L[i][t] (row t of X is final by then)
   for (int t = 0; t < NB - 1; ++t) {
     if (i > t) {
-      const double2 l = X[i][t];
-      for (int j = j0; j < t; j += 4) X[i][j] = zsub(X[i][j], zmul(l, X[t][j]));
-      if ((t & 3) == j0) X[i][t] = make_double2(-l.x, -l.y);
+      const double2 l = X(i, t);
+      for (int j = j0; j < t; j += 4) X(i, j) = zsub(X(i, j), zmul(l, X(t, j)));
+      if ((t & 3) == j0) X(i, t) = make_double2(-l.x, -l.y);
     }
     __syncthreads();
   }
+  // L11^-1 is unit lower triangular: zeros above the diagonal and beyond kb
   double2 *Li = linv_g + (long long)f * NB * NB;
 #pragma unroll
   for (int q = 0; q < NB * NB / 256; ++q) {
     const int idx = q * 256 + tid, r = idx / NB, c = idx - r * NB;
-    Li[idx] = (r < kb && c < kb) ? X[r][c] : make_double2(0.0, 0.0);
+    Li[idx] = (r < kb && c <= r) ? X(r, c) : make_double2(0.0, 0.0);
   }
   if (tid == 0 && zero) status[f] = 1;
 }
