@@ -1,12 +1,13 @@
-// Mixed-precision polarisability: Pi(z) = L diag(chi(z)) L^T with 16-bit MFMA
-// inputs and FP32 accumulation (precision form of the Pi build).
+// Mixed-precision polarisability: Pi(z) = L diag(chi(z)) L^T with 16-bit or
+// 8-bit MFMA inputs and FP32 accumulation (precision form of the Pi build).
 //
-// Each operand x is split into two 16-bit values, x ~ hi + lo with
-// hi = round16(x), lo = round16(x - hi), and the product is formed from three
+// Each operand x is split into two values of the form's type, x ~ hi + lo
+// with hi = round(x), lo = round(x - hi), and the product is formed from three
 // MFMA passes, hi*hi + hi*lo + lo*hi (the lo*lo term, relative size 2^-2p, is
 // dropped).  B = L is split once per call; the A operand L_Pk chi_k is formed
-// per frequency in FP32 from an FP32 copy of L and FP32-rounded chi (chi itself
-// is computed in FP64) and split in registers.
+// per frequency in FP32 from a copy of L (FP32; FP16 with the column scales
+// applied for FP8) and FP32-rounded chi (chi itself is computed in FP64) and
+// split in registers.
 //
 //   BF16X3: bf16 (8-bit significand) -> ~2^-16 relative per product
 //   FP16X3: fp16 (11-bit significand) with power-of-two scaling: columns of B
@@ -17,9 +18,10 @@
 //           aimed one binade higher -> ~2^-7 relative per product
 //
 // Tile: one 128 x 256 block of Pi per workgroup and frequency (8 waves of
-// 16 x 256, v_mfma_f32_16x16x32_{bf16,f16,fp8}; every B chunk staged in LDS
-// serves 128 rows); upper-triangle blocks only, the result written as 1 - Pi
-// (FP64) into the bordered matrix with its mirror.
+// 16 x 256, v_mfma_f32_16x16x32_{bf16,f16} or, for FP8, two K chunks per
+// v_mfma_f32_16x16x128_f8f6f4; every B chunk staged in LDS serves 128 rows);
+// upper-triangle blocks only, the result written as 1 - Pi (FP64) into the
+// bordered matrix with its mirror.
 #include "gwc_internal.h"
 
 namespace gwc {
@@ -86,9 +88,7 @@ struct Mix<e4m3> {
     h = (E)(hp & 0xff);
     l = (E)(lp & 0xff);
   }
-  static __device__ __forceinline__ f4 mfma(V a, V b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0, 0, 0);
-  }
+  // (products: mix_mfma128, two K chunks at a time)
 };
 
 // ---------------------------------------------------------------------------
@@ -249,17 +249,18 @@ mixed_chi_kernel(const double *__restrict__ chi_re, const double *__restrict__ c
   o[MX_KSTEP] = (float)chi_im[(long long)f * ldl + k] * s * g;
 }
 
-// The Pi build of every mixed form, with the K chunks in a three-stage LDS
-// ring.  One workgroup of 8 waves per 128 x 256 tile and frequency; wave w
-// covers rows 16 w and all 256 columns: 16 blocks of 16 x 16, Re and Im
-// accumulators.  Each K chunk (32 for the 16-bit forms, 64 for FP8) is
-// fetched two chunks ahead of its multiply: per wave two 1 KB pieces of each
-// split B operand (hi, lo) straight into LDS (buffer_load ... lds, 16 bytes
-// per lane at piece base + 16 lane: no registers, no padding) with the
-// chunk's FP32 chi, and the wave's own A rows (FP32 L) into registers, all in
-// operand-fragment order.  The stages are separate __shared__ objects and the
-// loop is unrolled by three, so each multiply names one stage and each fetch
-// another, and the compiler inserts no waits between them.
+// The Pi build of every mixed form, with the K chunks in a four-stage LDS
+// ring and one barrier per two chunks.  One workgroup of 8 waves per
+// 128 x 256 tile and frequency; wave w covers rows 16 w and all 256 columns:
+// 16 blocks of 16 x 16, Re and Im accumulators.  Each K chunk (32 for the
+// 16-bit forms, 64 for FP8) is fetched two chunks ahead of its multiply: per
+// wave two 1 KB pieces of each split B operand (hi, lo) straight into LDS
+// (buffer_load ... lds, 16 bytes per lane at piece base + 16 lane: no
+// registers, no padding) with the chunk's FP32 chi, and the wave's own A rows
+// into registers, all in operand-fragment order.  The stages are separate
+// __shared__ objects and the loop is unrolled by four, so each multiply names
+// its stages and each fetch others, and the compiler inserts no waits between
+// them.
 // Raw buffer resources (base, no stride, size in bytes; the gfx9 format word):
 // the hardware returns zeros past the size instead of faulting.
 constexpr int BUF_FORMAT_WORD = 0x00020000;
@@ -589,7 +590,7 @@ pi_build_mixed_async_kernel(const typename MixA<T>::E *__restrict__ Lf,
                             double2 *__restrict__ G, long long g_stride, int ldg) {
   using E = typename Mix<T>::E;
   constexpr int KC = MixK<T>::KC, AP = MixA<T>::AP;
-  // three stages as separate objects (the compiler then needs no wait between
+  // four stages as separate objects (the compiler then needs no wait between
   // a fetch into one and the reads of another); a stage's B pieces are 16 KB
   // of each split part in every form
   struct Stage {
