@@ -17,8 +17,17 @@
  *   - On error the outputs are unspecified, the status below is returned, no
  *     exception crosses the ABI and the process is never aborted;
  *     gwc_last_error() then describes the failure (thread-local).
- *   - Concurrent calls on one device from several host threads are
- *     serialised by the library.
+ *   - Calls from several host threads may run at once, each ordered on its own
+ *     stream (the request server's workers do so); the library's shared state
+ *     (its device-memory cache, a resident system's split operands, the
+ *     timing registry) is guarded by locks.  gwc_spectral_cumulant_noalloc is
+ *     the exception: see there.
+ *   - Device temporaries come from a library-owned cache of device blocks per
+ *     GPU: a block freed by a call is kept (up to half the device's memory)
+ *     and handed out again, to the same stream at once and to another stream
+ *     once the freeing stream has passed the block's last use; only a miss
+ *     calls hipMalloc, and a failed allocation first returns the idle blocks.
+ *     The cached bytes stay allocated until then or the process ends.
  */
 #ifndef GWC_H
 #define GWC_H
