@@ -78,7 +78,24 @@ void launch_chi(const double *eps, int n_occ, int n_virt, const double2 *z, int 
 }
 
 // ---------------------------------------------------------------------------
-// Pi build.  Grid: (n_tiles, ceil(F / PI_FB)).  Wave w of the workgroup owns
+// Workgroup -> (tile, frequency pair) so that the workgroups one XCD holds at
+// a time share a tile: workgroups go round-robin over the 8 XCDs, and each
+// XCD's consecutive workgroups take one tile for `group` consecutive
+// frequency pairs (two per CU of the XCD), so they read the same L rows,
+// chunk by chunk, from the XCD's L2.  Blocks of (tile, pair group) go to the
+// XCDs in turn.  False for the workgroups past the last pair.
+constexpr int PI_NXCD = 8;
+__device__ __forceinline__ bool pi_item(int wg, int n_tiles, int P, int group, int &tile, int &p) {
+  const int x = wg % PI_NXCD, j = wg / PI_NXCD;
+  const int blk = (j / group) * PI_NXCD + x;
+  const int g = blk / n_tiles;
+  tile = blk - g * n_tiles;
+  p = g * group + j % group;
+  return g * group < P && p < P;
+}
+
+// Pi build.  Grid: one workgroup per (tile, frequency pair), ordered by
+// pi_item.  Wave w of the workgroup owns
 // rows 32*(w/2) .. +32 and columns 32*(w%2) .. +32 of the 64 x 64 tile, i.e. a
 // 2 x 2 block of 16 x 16 MFMA outputs, for PI_FB frequencies, real and
 // imaginary parts: 16 accumulators of 4 doubles per lane.
@@ -88,19 +105,21 @@ void launch_chi(const double *eps, int n_occ, int n_virt, const double2 *z, int 
 __global__ void __launch_bounds__(PI_THREADS, 2)
 pi_build_f64_kernel(const double *__restrict__ Lp, int ldl, int n_aux,
                     const double *__restrict__ chi_re, const double *__restrict__ chi_im, int F,
-                    const int2 *__restrict__ tiles, double2 *__restrict__ G, long long g_stride,
-                    int ldg) {
+                    const int2 *__restrict__ tiles, int n_tiles, int group, double2 *__restrict__ G,
+                    long long g_stride, int ldg) {
   constexpr int T = PI_TILE, KC = PI_KC, FB = PI_FB, LDA = KC + 1;
   __shared__ double As[T * LDA];
   __shared__ double Bs[T * LDA];
   __shared__ double Cs[FB][2][KC];
 
+  int tile, pair;
+  if (!pi_item(blockIdx.x, n_tiles, (F + FB - 1) / FB, group, tile, pair)) return;  // the whole workgroup
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int2 tb = tiles[blockIdx.x];
+  const int2 tb = tiles[tile];
   const int P0 = tb.x * T, Q0 = tb.y * T;
-  const int f0 = blockIdx.y * FB;
+  const int f0 = pair * FB;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
   // on a diagonal tile the lower-left quadrant is the mirror of the upper-right
@@ -203,9 +222,13 @@ pi_build_f64_kernel(const double *__restrict__ Lp, int ldl, int n_aux,
 void launch_pi_build_f64(const double *Lp, int ldl, int n_aux, const double *chi_re,
                          const double *chi_im, int F, const int2 *tiles, int n_tiles,
                          double2 *G, long long g_stride, int ldg, hipStream_t stream) {
-  dim3 grid(n_tiles, (F + PI_FB - 1) / PI_FB);
-  pi_build_f64_kernel<<<grid, PI_THREADS, 0, stream>>>(Lp, ldl, n_aux, chi_re, chi_im, F, tiles,
-                                                       G, g_stride, ldg);
+  // (tile, pair-group) blocks, rounded up to a whole turn of the XCDs
+  const int P = (F + PI_FB - 1) / PI_FB;
+  const int group = P < 64 ? P : 64;
+  const long long blocks = (long long)n_tiles * ((P + group - 1) / group);
+  const long long wgs = (blocks + PI_NXCD - 1) / PI_NXCD * PI_NXCD * group;
+  pi_build_f64_kernel<<<(unsigned)wgs, PI_THREADS, 0, stream>>>(Lp, ldl, n_aux, chi_re, chi_im, F, tiles,
+                                                                n_tiles, group, G, g_stride, ldg);
 }
 
 }  // namespace gwc
